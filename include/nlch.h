@@ -1,0 +1,186 @@
+/*
+ * nlch.h -- C ABI of libnlch.so, the MI355X (gfx950) solver for the nonlocal
+ * phase-field model with obstacle potential and its multifidelity Monte Carlo
+ * estimator (arXiv 2310.10750).
+ *
+ * The model (Sec. 2.1, eq. nonl_CH_nm with beta2 = 0, the non-mass-conserving
+ * nonlocal Allen-Cahn case the paper names there):
+ *     du/dt + beta1 w = 0,   w = L u + dF_obs(u),
+ *     L u = c_gamma u - gamma * u                         (eq. nonl_operator)
+ *     F_obs(u) = c_F/2 (1 - u^2) + indicator of [-1, 1]   (eq. potential_obstacle)
+ * on the periodic unit square, discretised on an n x n lattice (h = 1/n) with
+ * nodal (lumped) quadrature of the convolution over the horizon disc
+ *     D = { d in Z^2 : |d|^2 <= R2 },  R2 = floor((delta n)^2 + 1e-9),
+ *     w_d = h^2 gamma(h |d|),  c_gamma_h = sum_{d in D} w_d (self term included),
+ *     xi_h = c_gamma_h - c_F                               (eq. xi_constant)
+ * and implicit Euler with the convolution explicit (Sec. 4):
+ *     u^k = clamp((u^{k-1} + tau beta1 (gamma*u^{k-1})) / (1 + tau beta1 xi_h), -1, 1),
+ * which the library evaluates in the algebraically equal difference form
+ *     v = u + c1 (c_F u - sum_{d != 0} w_d (u - u_{+d})),
+ *     c1 = tau beta1 / (1 + tau beta1 xi_h),   u' = clamp(v, -1, 1).
+ * The output of interest is f_1 = (1 + mean(u^T)) / 2 (eq. ooi).
+ *
+ * Conventions for every entry point:
+ *  - Status: 0 on success, else one of the NLCH_E* codes; the message of the
+ *    last failure on the calling thread is returned by nlch_last_error().
+ *  - All arguments are validated on the host before anything is enqueued, so
+ *    a call that fails validation leaves every buffer untouched.  Errors of
+ *    enqueued device work (NLCH_EDEVICE) may surface at a later call or when
+ *    the caller synchronises the stream.
+ *  - Device buffers are owned by the caller and must stay valid until the
+ *    enqueued work completes; the library only allocates small internal
+ *    tables (geometry, sample descriptors, graph caches) that it reuses.
+ *  - Lattice states are row-major, element (y, x) at index y*n + x, with the
+ *    element type given by the precision: double (NLCH_F64), float (NLCH_F32)
+ *    or IEEE binary16 (NLCH_F16_STORE: state stored in FP16, arithmetic in
+ *    FP32, every stored value rounded to nearest-even).
+ *  - hip_stream is a hipStream_t (NULL = the null stream).
+ *  - Calls that enqueue work on the same device buffers must not overlap.
+ */
+#ifndef NLCH_H
+#define NLCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define NLCH_OK 0
+#define NLCH_EINVAL (-1)       /* invalid argument (nothing enqueued)           */
+#define NLCH_EUNSUPPORTED (-2) /* valid model outside what this build supports  */
+#define NLCH_EDEVICE (-3)      /* HIP runtime error                              */
+#define NLCH_ENOMEM (-4)       /* internal table allocation failed               */
+
+/* Kernel gamma on |r| <= delta (Sec. 4, eq. kernel_gauss). */
+#define NLCH_KERNEL_CONSTANT 0 /* gamma(r) = amp                                 */
+#define NLCH_KERNEL_GAUSSIAN 1 /* gamma(r) = amp * exp(-r^2 / sigma^2)           */
+
+/* State element type / arithmetic. */
+#define NLCH_F64 0       /* FP64 storage, FP64 arithmetic                       */
+#define NLCH_F32 1       /* FP32 storage, FP32 arithmetic                       */
+#define NLCH_F16_STORE 2 /* FP16 storage, FP32 arithmetic                       */
+
+/* Algorithm selection (low byte) and flags. */
+#define NLCH_ALGO_AUTO 0     /* RESIDENT where a sample fits in LDS, else ROWRUN
+                                where built for the disc, else DIRECT          */
+#define NLCH_ALGO_DIRECT 1   /* per-site disc sum, one launch per step         */
+#define NLCH_ALGO_ROWRUN 2   /* disc as row runs of window sums, one launch per
+                                step (discs with R2 in nlch_rowrun_supported)  */
+#define NLCH_ALGO_RESIDENT 3 /* whole sample in LDS for all steps, one launch  */
+#define NLCH_ALGO_ACC64 0x100    /* accumulate disc sums in FP64 (F32/F16 only)  */
+#define NLCH_ALGO_NOGRAPH 0x200  /* enqueue launches directly, no graph replay   */
+#define NLCH_ALGO_CHECK_FINITE 0x400 /* reject non-finite u0 with NLCH_EINVAL;
+                                        synchronises hip_stream                 */
+
+/* One fidelity level ("model"): lattice, horizon, kernel and evolution
+ * parameters (Sec. 2.1 and Sec. 4). */
+typedef struct nlch_model {
+    int32_t n;           /* lattice size n x n on [0,1)^2, h = 1/n; n > 2m     */
+    int32_t kernel;      /* NLCH_KERNEL_*                                       */
+    double delta;        /* horizon; m = floor(sqrt(R2)) must be <= 48         */
+    double kernel_amp;   /* amp > 0                                             */
+    double kernel_sigma; /* Gaussian width > 0 (ignored for the constant kernel)*/
+    double c_F;          /* obstacle-potential constant > 0                     */
+    double beta1;        /* > 0                                                 */
+    double beta2;        /* must be 0 (else NLCH_EUNSUPPORTED)                  */
+    double tau;          /* time step > 0 with 1 + tau beta1 xi_h > 0           */
+} nlch_model;
+
+/* One sampled input of a batch: its model, its own c_F and kernel amplitude
+ * (the random parameters of Sec. 4), and the element offset of its n x n
+ * state inside the batch buffers. */
+typedef struct nlch_sample {
+    int32_t model;      /* index into the models array                          */
+    int32_t reserved;   /* must be 0                                            */
+    double c_F;         /* > 0                                                  */
+    double kernel_amp;  /* > 0                                                  */
+    int64_t offset;     /* element offset; states must not overlap             */
+} nlch_sample;
+
+/* Results of mfmc_estimate (K <= NLCH_MFMC_MAX_K models). */
+#define NLCH_MFMC_MAX_K 8
+typedef struct mfmc_result {
+    double q_mfmc;                     /* eq. MFMC_estimator                     */
+    double q_mc;                       /* mean of model 1 over its m_1 samples   */
+    double mean_mj[NLCH_MFMC_MAX_K];   /* mean of model j over its first m_j     */
+    double mean_mjm1[NLCH_MFMC_MAX_K]; /* over its first m_{j-1} (j >= 2)        */
+    double var[NLCH_MFMC_MAX_K];       /* sample variance over the first m_1     */
+    double rho[NLCH_MFMC_MAX_K];       /* correlation with model 1, first m_1    */
+    double alpha[NLCH_MFMC_MAX_K];     /* coefficients used (alpha[0] = 1)       */
+} mfmc_result;
+
+/* Disc geometry (host only, no device needed).  Writes R2, m = floor(sqrt(R2)),
+ * N = |D| and, if halfw != NULL, the row half-widths halfw[dy + m] =
+ * floor(sqrt(R2 - dy^2)) for dy = -m..m (cap >= 2m+1 entries).
+ * NLCH_EINVAL for n <= 0, a negative or non-finite delta, or a short cap. */
+int nlch_disc(int32_t n, double delta, int64_t *R2, int32_t *m, int64_t *N,
+              int32_t *halfw, int32_t cap);
+
+/* Discrete model constants (host only): c_gamma_h (kernel mass with the self
+ * term), xi_h = c_gamma_h - c_F and c1 = tau beta1 / (1 + tau beta1 xi_h), for
+ * the model's own c_F and amplitude.  Any output pointer may be NULL.
+ * NLCH_EINVAL if the model is invalid (see nlch_model). */
+int nlch_model_constants(const nlch_model *model, double *c_gamma_h,
+                         double *xi_h, double *c1);
+
+/* One time step of the scheme for a single n x n state (model's c_F and
+ * kernel_amp): u_out = step(u_in).  u_in, u_out: device arrays of n*n
+ * elements of the precision's type, distinct and non-overlapping (the stencil
+ * reads neighbours).  ooi_out: NULL, or a device array of 2 doubles that
+ * receives {mean(u_out), f_1(u_out)} (eq. ooi).  algo: NLCH_ALGO_DIRECT or
+ * NLCH_ALGO_ROWRUN (AUTO picks one), optionally | NLCH_ALGO_ACC64.  No initial
+ * projection: u_in is used as given.  Exactly one launch of the step kernel
+ * (plus one reduction launch if ooi_out != NULL). */
+int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
+              const void *u_in, void *u_out, double *ooi_out, void *hip_stream);
+
+/* Solve a batch: for every sample s, u^0 = clamp(state_s, -1, 1) (the initial
+ * datum projected onto [-1, 1]), nsteps steps of the scheme with the sample's
+ * model, c_F and amplitude, then u^nsteps is left in state_s and
+ * {mean, f_1} in ooi_out[2s], ooi_out[2s+1] (FP64).
+ * models: n_models >= 1 host structs; samples: n_samples >= 1 host structs.
+ * state: device buffer holding every sample's n*n elements at its offset
+ * (in: u0, out: final state).  scratch: device buffer of the same extent,
+ * used as the ping-pong partner (may be NULL when every sample runs
+ * RESIDENT).  ooi_out: device array of 2*n_samples doubles.
+ * Samples of different models (uneven n and horizon) may be mixed; the
+ * library never reorders outputs.  Without NLCH_ALGO_NOGRAPH the sequence of
+ * launches is captured once into a HIP graph per distinct call signature
+ * (buffers, batch, nsteps, algo) and replayed on later calls.
+ * NaN in u0 propagates to the outputs unless NLCH_ALGO_CHECK_FINITE is set. */
+int nlch_solve_batch(const nlch_model *models, int32_t n_models,
+                     const nlch_sample *samples, int64_t n_samples,
+                     int32_t nsteps, int32_t precision, int32_t algo,
+                     void *state, void *scratch, double *ooi_out,
+                     void *hip_stream);
+
+/* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
+ * y_dev[j]: device array of at least m[j] doubles, y_dev[j][i] the output of
+ * model j+1 for parameter draw i (draws shared across models: model j+1 uses
+ * draws 0..m[j]-1).  m: host array, non-decreasing, m[0] >= 2.
+ * alpha: NULL (estimate alpha_j = rho_{1j} sigma_1 / sigma_j, eq. alpha, from
+ * the first m[0] shared draws; zero-variance models get alpha = 0) or K-1 host
+ * values for models 2..K.  Moments are accumulated in FP64 on the device
+ * (two-pass); the call synchronises hip_stream and fills *out on the host.
+ * Q_MFMC = mean_1(m_1) + sum_j alpha_j (mean_j(m_j) - mean_j(m_{j-1}))
+ * (eq. MFMC_estimator). */
+int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev,
+                  const double *alpha, mfmc_result *out, void *hip_stream);
+
+/* Largest radius-squared values R2 for which the ROWRUN / RESIDENT kernels are
+ * compiled: writes up to cap values into r2_list and returns their count. */
+int nlch_rowrun_supported(int64_t *r2_list, int32_t cap);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *nlch_last_error(void);
+
+/* ABI version (increments on any change to this header). */
+int nlch_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLCH_H */

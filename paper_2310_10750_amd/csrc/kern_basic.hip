@@ -1,0 +1,249 @@
+// Elementwise and reduction kernels, and the per-site ("direct") disc-sum step.
+//
+//  * k_project: u^0 = clamp(u0, -1, 1), the projection of the initial datum
+//    onto the admissible set [-1, 1] (obstacle potential, Sec. 2).
+//  * k_count_nonfinite: optional validation of u0.
+//  * k_ooi: per-sample FP64 sum -> mean and f_1 = (1 + mean)/2 (eq. ooi).
+//  * k_direct: one step, every site summing over the whole horizon disc in
+//    difference form  Lsum = sum_{d != 0} e_d (u_i - u_{i+d})  (eq.
+//    nonl_operator with nodal quadrature), then the projected update.  Halo
+//    tile staged in LDS; any horizon up to kMaxM.
+#include "nlch_device.h"
+
+namespace nlch {
+
+namespace {
+
+constexpr int kElemThreads = 256;
+constexpr int kElemItems = 8;
+
+template <class TS>
+__global__ __launch_bounds__(kElemThreads) void k_project(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    int64_t nn, int chunks, const TS *src, TS *dst) {
+    const int b = blockIdx.x;
+    const SampleDesc d = sd[ids[b / chunks]];
+    const int64_t chunk = (int64_t)kElemThreads * kElemItems;
+    const int64_t lo = (int64_t)(b % chunks) * chunk;
+    const int64_t hi = lo + chunk < nn ? lo + chunk : nn;
+    const TS *s = src + d.offset;
+    TS *o = dst + d.offset;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kElemThreads) {
+        TS v = s[i];
+        o[i] = v < TS(-1) ? TS(-1) : (v > TS(1) ? TS(1) : v);
+    }
+}
+
+template <class TS>
+__global__ __launch_bounds__(kElemThreads) void k_count_nonfinite(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    int64_t nn, int chunks, const TS *__restrict__ src,
+    unsigned int *__restrict__ counter) {
+    const int b = blockIdx.x;
+    const SampleDesc d = sd[ids[b / chunks]];
+    const int64_t chunk = (int64_t)kElemThreads * kElemItems;
+    const int64_t lo = (int64_t)(b % chunks) * chunk;
+    const int64_t hi = lo + chunk < nn ? lo + chunk : nn;
+    const TS *s = src + d.offset;
+    unsigned int bad = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kElemThreads) {
+        double v = (double)s[i];
+        bad += (v - v != 0.0) ? 1u : 0u;  // NaN or +-inf
+    }
+    if (bad) atomicAdd(counter, bad);
+}
+
+template <class TS>
+__global__ __launch_bounds__(256) void k_ooi(const SampleDesc *__restrict__ sd,
+                                             const int32_t *__restrict__ ids,
+                                             int64_t nn, const TS *__restrict__ st,
+                                             double *__restrict__ ooi) {
+    __shared__ double red[4];
+    const int sidx = ids[blockIdx.x];
+    const SampleDesc d = sd[sidx];
+    const TS *s = st + d.offset;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < nn; i += 256) acc += (double)s[i];
+    double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        double mean = tot / (double)nn;
+        ooi[2 * (int64_t)sidx] = mean;
+        ooi[2 * (int64_t)sidx + 1] = 0.5 * (1.0 + mean);
+    }
+}
+
+constexpr int kDirTX = 64, kDirTY = 16, kDirThreads = 256;
+
+template <class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(kDirThreads) void k_direct(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const TA *__restrict__ ew,
+    const TS *__restrict__ in, TS *__restrict__ out, int tiles_x,
+    int tiles_per_sample, int nblocks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TA *tile = reinterpret_cast<TA *>(smem_raw);
+    const int n = geo->n, m = geo->m;
+    const int b = xcd_remap(blockIdx.x, nblocks);
+    const SampleDesc d = sd[ids[b / tiles_per_sample]];
+    const int t = b % tiles_per_sample;
+    const int x0 = (t % tiles_x) * kDirTX, y0 = (t / tiles_x) * kDirTY;
+    const TS *src = in + d.offset;
+    TS *dst = out + d.offset;
+    const int W = kDirTX + 2 * m, H = kDirTY + 2 * m;
+
+    for (int i = threadIdx.x; i < W * H; i += kDirThreads) {
+        const int r = i / W, c = i - r * W;
+        int gy = (y0 - m + r) % n;
+        gy += gy < 0 ? n : 0;
+        int gx = (x0 - m + c) % n;
+        gx += gx < 0 ? n : 0;
+        tile[i] = to_acc<TA>(src[(int64_t)gy * n + gx]);
+    }
+    __syncthreads();
+
+    const TA a = coef_a<TA>(d), bb = coef_b<TA>(d);
+    const TA *ewm = ew + geo->e_off;
+    const int lx = threadIdx.x & 63;
+    for (int ly = threadIdx.x >> 6; ly < kDirTY; ly += kDirThreads / 64) {
+        const int y = y0 + ly, x = x0 + lx;
+        const TA *cen = tile + (ly + m) * W + lx + m;
+        const TA uc = *cen;
+        TA acc = TA(0);
+        for (int dy = -m; dy <= m; ++dy) {
+            const int ady = dy < 0 ? -dy : dy;
+            const int w = geo->halfw[ady];
+            const TA *row = cen + dy * W;
+            for (int dx = -w; dx <= w; ++dx) {
+                const TA diff = uc - row[dx];
+                if (GAUSS) {
+                    const int adx = dx < 0 ? -dx : dx;
+                    acc += ewm[ady * (m + 1) + adx] * diff;
+                } else {
+                    acc += diff;
+                }
+            }
+        }
+        if (y < n && x < n) dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(uc, acc, a, bb));
+    }
+}
+
+template <class TS>
+inline int chunks_for(int64_t nn) {
+    const int64_t chunk = (int64_t)kElemThreads * kElemItems;
+    return (int)((nn + chunk - 1) / chunk);
+}
+
+}  // namespace
+
+hipError_t launch_project(int prec, const Group &g, const void *src, void *dst,
+                          hipStream_t s) {
+    const int64_t nn = (int64_t)g.n * g.n;
+    const int ch = chunks_for<float>(nn);
+    dim3 grid((unsigned)(ch * g.nids)), block(kElemThreads);
+    switch (prec) {
+        case kF64:
+            hipLaunchKernelGGL((k_project<double>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const double *)src, (double *)dst);
+            break;
+        case kF32:
+            hipLaunchKernelGGL((k_project<float>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const float *)src, (float *)dst);
+            break;
+        default:
+            hipLaunchKernelGGL((k_project<half_t>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const half_t *)src, (half_t *)dst);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(int prec, const Group &g, const void *src,
+                                  unsigned int *counter, hipStream_t s) {
+    const int64_t nn = (int64_t)g.n * g.n;
+    const int ch = chunks_for<float>(nn);
+    dim3 grid((unsigned)(ch * g.nids)), block(kElemThreads);
+    switch (prec) {
+        case kF64:
+            hipLaunchKernelGGL((k_count_nonfinite<double>), grid, block, 0, s, g.sd, g.ids, nn,
+                               ch, (const double *)src, counter);
+            break;
+        case kF32:
+            hipLaunchKernelGGL((k_count_nonfinite<float>), grid, block, 0, s, g.sd, g.ids, nn,
+                               ch, (const float *)src, counter);
+            break;
+        default:
+            hipLaunchKernelGGL((k_count_nonfinite<half_t>), grid, block, 0, s, g.sd, g.ids, nn,
+                               ch, (const half_t *)src, counter);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi,
+                      int, hipStream_t s) {
+    const int64_t nn = (int64_t)g.n * g.n;
+    dim3 grid((unsigned)g.nids), block(256);
+    switch (prec) {
+        case kF64:
+            hipLaunchKernelGGL((k_ooi<double>), grid, block, 0, s, g.sd, g.ids, nn,
+                               (const double *)state, ooi);
+            break;
+        case kF32:
+            hipLaunchKernelGGL((k_ooi<float>), grid, block, 0, s, g.sd, g.ids, nn,
+                               (const float *)state, ooi);
+            break;
+        default:
+            hipLaunchKernelGGL((k_ooi<half_t>), grid, block, 0, s, g.sd, g.ids, nn,
+                               (const half_t *)state, ooi);
+            break;
+    }
+    return hipGetLastError();
+}
+
+template <class TA>
+static const TA *ew_for(const Group &g);
+template <>
+const float *ew_for<float>(const Group &g) { return g.ewf; }
+template <>
+const double *ew_for<double>(const Group &g) { return g.ewd; }
+
+template <class TS, class TA>
+static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStream_t s) {
+    const int tiles_x = (g.n + kDirTX - 1) / kDirTX;
+    const int tiles_y = (g.n + kDirTY - 1) / kDirTY;
+    const int tps = tiles_x * tiles_y;
+    const int64_t nb = (int64_t)tps * g.nids;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = sizeof(TA) * (size_t)(kDirTX + 2 * g.m) * (kDirTY + 2 * g.m);
+    dim3 grid((unsigned)nb), block(kDirThreads);
+    if (g.kernel == 1) {
+        auto f = k_direct<TS, TA, true>;
+        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
+                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb);
+    } else {
+        auto f = k_direct<TS, TA, false>;
+        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
+                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_step(int prec, bool acc64, const Group &g, const void *in,
+                              void *out, hipStream_t s) {
+    switch (prec) {
+        case kF64:
+            return direct_typed<double, double>(g, in, out, s);
+        case kF32:
+            return acc64 ? direct_typed<float, double>(g, in, out, s)
+                         : direct_typed<float, float>(g, in, out, s);
+        default:
+            return acc64 ? direct_typed<half_t, double>(g, in, out, s)
+                         : direct_typed<half_t, float>(g, in, out, s);
+    }
+}
+
+}  // namespace nlch

@@ -1,0 +1,324 @@
+// Row-run ("window sum") kernels for the horizon disc, with the disc geometry
+// fixed at compile time.
+//
+// The nodal-quadrature convolution over the disc D (eq. nonl_operator) is
+// evaluated per output site (y, x) as a sum over disc rows dy of horizontal
+// window sums
+//     G(y, x) = sum_{dy=-m}^{m} g(|dy|) H_{w(dy)}(y + dy, x),
+//     H_w(r, x) = sum_{|dx| <= w} g(|dx|) u(r, x + dx),   w(dy) = isqrt(R2 - dy^2),
+// where g == 1 for the constant kernel and g(k) = exp(-k^2 h^2 / sigma^2) for
+// the Gaussian kernel, whose weights factor as g(|dy|) g(|dx|).  The unit
+// operator sum of the difference form is then Lsum = ce u - G with
+// ce = sum_{d in D} g(|dy|) g(|dx|).  Per site this costs 2m + (2m+1) adds
+// (plus m + 2m+1 multiplies for the Gaussian) instead of |D| ~ pi m^2.
+//
+// A lane owns R adjacent columns and walks down the rows.  Window sums of one
+// input row are grown incrementally (H_k = H_{k-1} + g(k) (u(x-k) + u(x+k)))
+// and each is added, as soon as it is formed, into every pending output row
+// whose disc row has that half-width.  All register indices are compile-time
+// constants (template loops), so nothing is demoted to scratch memory.
+#pragma once
+
+#include <type_traits>
+
+#include "nlch_device.h"
+
+namespace nlch {
+
+constexpr int cisqrt(int v) {
+    int r = 0;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+template <class T, int N>
+struct CArr {
+    T v[N];
+    constexpr T operator[](int i) const { return v[i]; }
+};
+
+// Compile-time disc geometry: half-widths, and the disc rows dy grouped by
+// half-width (rows whose window sum has width k are dy_by_w[start[k]] ..
+// dy_by_w[start[k+1]-1]).
+template <int R2>
+struct Disc {
+    static constexpr int M = cisqrt(R2);
+    static constexpr int P = 2 * M + 1;
+    static constexpr int w(int ady) { return cisqrt(R2 - ady * ady); }
+    static constexpr CArr<int, P> make_dy() {
+        CArr<int, P> a{};
+        int e = 0;
+        for (int k = 0; k <= M; ++k)
+            for (int dy = -M; dy <= M; ++dy)
+                if (w(dy < 0 ? -dy : dy) == k) a.v[e++] = dy;
+        return a;
+    }
+    static constexpr CArr<int, M + 2> make_start() {
+        CArr<int, M + 2> a{};
+        int e = 0;
+        for (int k = 0; k <= M; ++k) {
+            a.v[k] = e;
+            for (int dy = -M; dy <= M; ++dy)
+                if (w(dy < 0 ? -dy : dy) == k) ++e;
+        }
+        a.v[M + 1] = e;
+        return a;
+    }
+    static constexpr CArr<int, P> dy_by_w = make_dy();
+    static constexpr CArr<int, M + 2> start = make_start();
+};
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+constexpr int cabs(int v) { return v < 0 ? -v : v; }
+
+// Window sums of one input row for column c (window values win[c .. c+2M])
+// grown incrementally, each added into the outputs that use its half-width:
+// add(dy, value) receives g(|dy|) * H_{w(dy)} (or H for the constant kernel).
+template <int R2, bool GAUSS, class TA, class Add>
+__device__ __forceinline__ void row_windows(const TA *win, const TA *g, Add &&add) {
+    using D = Disc<R2>;
+    constexpr int M = D::M;
+    TA H = GAUSS ? g[0] * win[M] : win[M];
+    sfor<0, M + 1>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k > 0) {
+            const TA pair = win[M - k] + win[M + k];
+            H = GAUSS ? (H + g[k] * pair) : (H + pair);
+        }
+        sfor<D::start[k], D::start[k + 1]>([&](auto E) {
+            constexpr int dy = D::dy_by_w[E];
+            add(dy, GAUSS ? g[cabs(dy)] * H : H);
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Streaming step: one workgroup = NW waves stacked vertically over a tile of
+// 64R columns x NW*B rows of one sample.  The halo tile (rows and columns
+// widened by m, wrapped periodically) is staged in LDS once; each wave walks
+// its B output rows with a ring of 2m+1 accumulator rows and writes finished
+// sites straight to the output buffer.
+// ---------------------------------------------------------------------------
+template <int R2, int R, int NW, class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(NW * 64) void k_rowrun(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const TS *__restrict__ in,
+    TS *__restrict__ out, int B, int tiles_x, int tiles_per_sample, int nblocks) {
+    constexpr int M = Disc<R2>::M, P = Disc<R2>::P;
+    constexpr int TX = 64 * R;
+    constexpr int TW = TX + 2 * M;
+    constexpr int WIN = 2 * M + R;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TS *tile = reinterpret_cast<TS *>(smem_raw);
+
+    const int n = geo->n;
+    const int bidx = xcd_remap(blockIdx.x, nblocks);
+    const SampleDesc d = sd[ids[bidx / tiles_per_sample]];
+    const int t = bidx % tiles_per_sample;
+    const int TY = NW * B;
+    const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+    const TS *src = in + d.offset;
+    TS *dst = out + d.offset;
+
+    // Stage rows y0-M .. y0+TY+M-1, columns x0-M .. x0+TX+M-1 (periodic).
+    const int rows_tile = TY + 2 * M;
+    for (int i = threadIdx.x; i < rows_tile * TW; i += NW * 64) {
+        const int r = i / TW, c = i - r * TW;
+        int gy = (y0 - M + r) % n;
+        gy += gy < 0 ? n : 0;
+        int gx = (x0 - M + c) % n;
+        gx += gx < 0 ? n : 0;
+        tile[i] = src[(int64_t)gy * n + gx];
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int c0 = lane * R;
+    const int rowbase = wave * B;
+    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    TA g[M + 1];
+#pragma unroll
+    for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
+
+    TA acc[P][R];
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[i][c] = TA(0);
+
+    const int rows = B + 2 * M;
+    for (int pb = 0; pb < rows; pb += P) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int p = pb + i;
+            if (p < rows) {
+                const TS *rp = tile + (rowbase + p) * TW + c0;
+                TA win[WIN];
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) win[j] = to_acc<TA>(rp[j]);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    // input row p feeds output q = p - M - dy, ring slot q mod P
+                    row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
+                        acc[((i - M - dy) % P + P) % P][c] += v;
+                    });
+                }
+                // Output q = p - 2M is complete (ring slot (i+1) mod P).
+                const int done = (i + 1) % P;
+                const int q = p - 2 * M;
+                if (q >= 0) {
+                    const int ly = rowbase + q;
+                    const int y = y0 + ly;
+                    const TS *cen = tile + (ly + M) * TW + c0 + M;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        const int x = x0 + c0 + c;
+                        const TA u = to_acc<TA>(cen[c]);
+                        const TA lsum = ce * u - acc[done][c];
+                        if (y < n && x < n)
+                            dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[done][c] = TA(0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident multi-step kernel: one workgroup holds one whole n x n sample
+// in LDS (rows padded with an m-column periodic halo) and runs every step
+// without touching HBM.  Threads own R columns x B rows of the state in
+// registers; per step they publish the state to LDS, then walk their band
+// (B + 2m input rows, fully unrolled, static accumulator indices) and update
+// their own sites in registers.  The initial projection and the final FP64
+// output-of-interest reduction are fused in.
+// ---------------------------------------------------------------------------
+template <int R2, int R, int B, class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(512) void k_resident(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
+    double *__restrict__ ooi, int tpb) {
+    constexpr int M = Disc<R2>::M;
+    constexpr int WIN = 2 * M + R;
+    constexpr int ROWS = B + 2 * M;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TS *lds = reinterpret_cast<TS *>(smem_raw);
+    __shared__ double red[16];
+
+    const int n = geo->n;
+    const int TW = n + 2 * M;
+    const int sidx = ids[blockIdx.x];
+    const SampleDesc d = sd[sidx];
+    TS *g_state = state + d.offset;
+    // band is uniform per wave (tpb % 64 == 0): keep its arithmetic scalar
+    const int band = __builtin_amdgcn_readfirstlane(threadIdx.x / tpb);
+    const int xb = (threadIdx.x - band * tpb) * R;
+    const int y0 = band * B;
+    int rstart = (y0 - M) % n;  // first input row of the band walk
+    rstart += rstart < 0 ? n : 0;
+    const int xr = xb + R <= n ? xb : n - R;  // in-row read position for idle lanes
+
+    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    TA g[M + 1];
+#pragma unroll
+    for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
+
+    // Load and project u0 onto [-1, 1].
+    TA st[B][R];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int y = y0 + q, x = xb + c;
+            TA v = TA(0);
+            if (y < n && x < n) v = to_acc<TA>(g_state[(int64_t)y * n + x]);
+            st[q][c] = clamp1(v);
+        }
+
+    for (int step = 0; step < nsteps; ++step) {
+        // Publish the state (and its periodic column halo) to LDS.
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int y = y0 + q;
+            if (y < n) {
+                TS *row = lds + y * TW + M;
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const int x = xb + c;
+                    if (x < n) {
+                        const TS v = to_store<TS>(st[q][c]);
+                        row[x] = v;
+                        if (x < M) row[x + n] = v;
+                        if (x >= n - M) row[x - n] = v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        TA acc[B][R];
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[q][c] = TA(0);
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+            int r = rstart + i;  // scalar: wrap onto the torus
+            while (r >= n) r -= n;
+            const TS *rp = lds + r * TW + xr;
+            TA win[WIN];
+#pragma unroll
+            for (int j = 0; j < WIN; ++j) win[j] = to_acc<TA>(rp[j]);
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                // input row i feeds output q = i - M - dy
+                row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
+                    const int q = i - M - dy;
+                    if (q >= 0 && q < B) acc[q][c] += v;
+                });
+            }
+            // Output row q = i - 2M is complete: update in registers.
+            const int q = i - 2 * M;
+            if (q >= 0 && q < B) {
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const TA u = st[q][c];
+                    const TA lsum = ce * u - acc[q][c];
+                    st[q][c] = to_acc<TA>(to_store<TS>(update<TA>(u, lsum, a, bcoef)));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Write back and reduce the output of interest in FP64.
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int y = y0 + q, x = xb + c;
+            if (y < n && x < n) {
+                g_state[(int64_t)y * n + x] = to_store<TS>(st[q][c]);
+                part += (double)st[q][c];
+            }
+        }
+    const double tot = block_sum(part, red);
+    if (threadIdx.x == 0) {
+        const double mean = tot / ((double)n * n);
+        ooi[2 * (int64_t)sidx] = mean;
+        ooi[2 * (int64_t)sidx + 1] = 0.5 * (1.0 + mean);
+    }
+}
+
+}  // namespace nlch

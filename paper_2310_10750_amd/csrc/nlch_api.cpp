@@ -1,0 +1,727 @@
+// Host runtime behind the C ABI of include/nlch.h: argument validation, disc
+// geometry and kernel tables, per-sample coefficients, launch grouping, and
+// HIP-graph capture/replay of whole solves.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nlch.h"
+#include "nlch_internal.h"
+
+namespace nlch {
+// per-type-pair units (kern_rowrun_*.hip)
+#define NLCH_DECL(SUF)                                                                   \
+    bool rowrun_has_##SUF(int R2);                                                       \
+    bool resident_has_##SUF(int R2, int n);                                              \
+    hipError_t rowrun_step_##SUF(const Group &g, const void *in, void *out, hipStream_t s); \
+    hipError_t resident_##SUF(const Group &g, void *state, int nsteps, double *ooi,      \
+                              hipStream_t s);
+NLCH_DECL(f64)
+NLCH_DECL(f32)
+NLCH_DECL(f16)
+#undef NLCH_DECL
+
+// Row-run and resident kernels exist for FP64 arithmetic on FP64 state and
+// FP32 arithmetic on FP32/FP16 state; FP64 accumulation of narrower states
+// (NLCH_ALGO_ACC64) runs on the direct kernel.
+bool rowrun_supported(int prec, bool acc64, int R2, int) {
+    switch (prec) {
+        case kF64: return rowrun_has_f64(R2);
+        case kF32: return !acc64 && rowrun_has_f32(R2);
+        default: return !acc64 && rowrun_has_f16(R2);
+    }
+}
+
+bool resident_supported(int prec, bool acc64, int R2, int, int n) {
+    switch (prec) {
+        case kF64: return resident_has_f64(R2, n);
+        case kF32: return !acc64 && resident_has_f32(R2, n);
+        default: return !acc64 && resident_has_f16(R2, n);
+    }
+}
+
+hipError_t launch_rowrun_step(int prec, bool, const Group &g, const void *in, void *out,
+                              hipStream_t s) {
+    switch (prec) {
+        case kF64: return rowrun_step_f64(g, in, out, s);
+        case kF32: return rowrun_step_f32(g, in, out, s);
+        default: return rowrun_step_f16(g, in, out, s);
+    }
+}
+
+hipError_t launch_resident(int prec, bool, const Group &g, void *state, int nsteps,
+                           double *ooi, hipStream_t s) {
+    switch (prec) {
+        case kF64: return resident_f64(g, state, nsteps, ooi, s);
+        case kF32: return resident_f32(g, state, nsteps, ooi, s);
+        default: return resident_f16(g, state, nsteps, ooi, s);
+    }
+}
+
+int rowrun_r2_list(int64_t *out, int cap) {
+    static const int64_t list[] = {1, 4, 9, 16, 25, 64, 256, 272, 1024};
+    const int cnt = (int)(sizeof(list) / sizeof(list[0]));
+    for (int i = 0; i < cnt && i < cap; ++i) out[i] = list[i];
+    return cnt;
+}
+
+}  // namespace nlch
+
+using namespace nlch;
+
+// ------------------------------------------------------------------ errors --
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                             \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return fail(NLCH_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------- geometry --
+
+static int64_t isqrt64(int64_t v) {
+    if (v <= 0) return 0;
+    int64_t r = (int64_t)std::sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+struct ModelInfo {
+    int64_t R2 = 0, N = 0;
+    int m = 0;
+    std::vector<int32_t> halfw;  // |dy| = 0..m
+    double sum_e = 0.0;          // sum_{d in D} e_d, e_d exact 2-D unit weights
+    double ce_sep = 0.0;         // sum_{d in D} g(|dy|) g(|dx|)
+    std::vector<double> g;       // g(k), k = 0..m
+    std::vector<double> e2;      // e(|dy|, |dx|), (m+1) x (m+1)
+};
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validates a model and builds its tables (host only, no device work).
+static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) {
+    if (md.n < 3 || md.n > 32768)
+        return fail(NLCH_EINVAL, "%s: n = %d outside [3, 32768]", what, md.n);
+    if (md.kernel != NLCH_KERNEL_CONSTANT && md.kernel != NLCH_KERNEL_GAUSSIAN)
+        return fail(NLCH_EINVAL, "%s: unknown kernel %d", what, md.kernel);
+    if (!std::isfinite(md.delta) || md.delta < 0.0 || md.delta * md.n > 1e6)
+        return fail(NLCH_EINVAL, "%s: delta must be finite and >= 0", what);
+    if (!finite_pos(md.kernel_amp)) return fail(NLCH_EINVAL, "%s: kernel_amp must be > 0", what);
+    if (md.kernel == NLCH_KERNEL_GAUSSIAN && !finite_pos(md.kernel_sigma))
+        return fail(NLCH_EINVAL, "%s: kernel_sigma must be > 0", what);
+    if (!finite_pos(md.c_F)) return fail(NLCH_EINVAL, "%s: c_F must be > 0", what);
+    if (!finite_pos(md.beta1)) return fail(NLCH_EINVAL, "%s: beta1 must be > 0", what);
+    if (!std::isfinite(md.beta2) || md.beta2 < 0.0)
+        return fail(NLCH_EINVAL, "%s: beta2 must be finite and >= 0", what);
+    if (md.beta2 != 0.0)
+        return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 needs a coupled solve per step; "
+                    "this build implements beta2 = 0", what);
+    if (!finite_pos(md.tau)) return fail(NLCH_EINVAL, "%s: tau must be > 0", what);
+
+    const double r = md.delta * (double)md.n;
+    mi.R2 = (int64_t)std::floor(r * r + 1e-9);
+    mi.m = (int)isqrt64(mi.R2);
+    if (mi.m > kMaxM)
+        return fail(NLCH_EUNSUPPORTED, "%s: horizon of %d lattice units exceeds %d", what, mi.m,
+                    kMaxM);
+    if (md.n <= 2 * mi.m)
+        return fail(NLCH_EINVAL, "%s: lattice n = %d must exceed twice the horizon (%d)", what,
+                    md.n, mi.m);
+    const int m = mi.m;
+    mi.halfw.resize(m + 1);
+    mi.N = 0;
+    for (int dy = -m; dy <= m; ++dy) {
+        const int w = (int)isqrt64(mi.R2 - (int64_t)dy * dy);
+        if (dy >= 0) mi.halfw[dy] = w;
+        mi.N += 2 * w + 1;
+    }
+    const double h = 1.0 / md.n;
+    mi.g.assign(m + 1, 1.0);
+    mi.e2.assign((size_t)(m + 1) * (m + 1), 1.0);
+    if (md.kernel == NLCH_KERNEL_GAUSSIAN) {
+        const double s2 = md.kernel_sigma * md.kernel_sigma;
+        for (int k = 0; k <= m; ++k) mi.g[k] = std::exp(-(double)k * k * h * h / s2);
+        for (int i = 0; i <= m; ++i)
+            for (int j = 0; j <= m; ++j)
+                mi.e2[(size_t)i * (m + 1) + j] = std::exp(-(double)(i * i + j * j) * h * h / s2);
+    }
+    mi.sum_e = 0.0;
+    mi.ce_sep = 0.0;
+    for (int dy = -m; dy <= m; ++dy) {
+        const int ady = dy < 0 ? -dy : dy;
+        const int w = mi.halfw[ady];
+        for (int dx = -w; dx <= w; ++dx) {
+            const int adx = dx < 0 ? -dx : dx;
+            mi.sum_e += mi.e2[(size_t)ady * (m + 1) + adx];
+            mi.ce_sep += mi.g[ady] * mi.g[adx];
+        }
+    }
+    return NLCH_OK;
+}
+
+struct Coef {
+    double c_gamma_h, xi_h, c1, a, b;
+};
+
+static int sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, double amp,
+                       Coef &c, const char *what) {
+    const double h2 = 1.0 / ((double)md.n * md.n);
+    c.c_gamma_h = h2 * amp * mi.sum_e;
+    c.xi_h = c.c_gamma_h - c_F;
+    const double tb = md.tau * md.beta1;
+    const double den = 1.0 + tb * c.xi_h;
+    if (!(den > 0.0))
+        return fail(NLCH_EINVAL, "%s: 1 + tau*beta1*xi_h = %g must be > 0", what, den);
+    c.c1 = tb / den;
+    c.a = c.c1 * c_F;
+    c.b = c.c1 * h2 * amp;
+    return NLCH_OK;
+}
+
+// ------------------------------------------------------------ device state --
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Device tables of one batch signature.
+struct Batch {
+    std::vector<uint8_t> key;
+    int device = -1;
+    DevBuf geo, ewf, ewd, sd, ids;
+    std::vector<Group> groups;           // launch groups
+    std::vector<int> variant;            // per group
+    std::map<std::vector<uint8_t>, hipGraphExec_t> graphs;
+    ~Batch() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    }
+};
+
+struct DevCtx {
+    hipStream_t capture = nullptr;
+    unsigned int *counter = nullptr;   // non-finite counter (device)
+    unsigned int *counter_h = nullptr; // pinned host copy
+    double *mom = nullptr;             // moments (device)
+    double *mom_h = nullptr;           // pinned host copy
+};
+
+std::mutex g_mu;
+std::map<int, DevCtx> g_dev;
+std::vector<std::unique_ptr<Batch>> g_batches;  // most recent last
+constexpr size_t kMaxBatches = 32;
+
+int dev_ctx(DevCtx **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    DevCtx &c = g_dev[dev];
+    if (!c.capture) {
+        HIP_TRY(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+        HIP_TRY(hipMalloc((void **)&c.counter, sizeof(unsigned int)));
+        HIP_TRY(hipHostMalloc((void **)&c.counter_h, sizeof(unsigned int), hipHostMallocDefault));
+        HIP_TRY(hipMalloc((void **)&c.mom, sizeof(double) * 8 * NLCH_MFMC_MAX_K));
+        HIP_TRY(hipHostMalloc((void **)&c.mom_h, sizeof(double) * 8 * NLCH_MFMC_MAX_K,
+                              hipHostMallocDefault));
+    }
+    *out = &c;
+    return NLCH_OK;
+}
+
+template <class T>
+void append_bytes(std::vector<uint8_t> &k, const T &v) {
+    const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
+size_t prec_size(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }
+
+float rne_f32(double v) { return (float)v; }
+
+// Chooses the kernel variant for a model under the requested algorithm.
+int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nlch_model &md,
+                   bool batch, int *variant) {
+    const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n);
+    const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
+    switch (base) {
+        case NLCH_ALGO_AUTO:
+            *variant = res ? kResident : (row ? kRowrun : kDirect);
+            return NLCH_OK;
+        case NLCH_ALGO_DIRECT:
+            *variant = kDirect;
+            return NLCH_OK;
+        case NLCH_ALGO_ROWRUN:
+            if (!row)
+                return fail(NLCH_EUNSUPPORTED, "ROWRUN is not built for R2 = %lld",
+                            (long long)mi.R2);
+            *variant = kRowrun;
+            return NLCH_OK;
+        case NLCH_ALGO_RESIDENT:
+            if (!batch) return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
+            if (!res)
+                return fail(NLCH_EUNSUPPORTED,
+                            "RESIDENT needs n <= 128, a sample that fits in LDS and a built "
+                            "R2 (n = %d, R2 = %lld)", md.n, (long long)mi.R2);
+            *variant = kResident;
+            return NLCH_OK;
+        default:
+            return fail(NLCH_EINVAL, "unknown algorithm %d", base);
+    }
+}
+
+// Builds (or finds) the device tables for a batch.
+int get_batch(const nlch_model *models, int32_t n_models, const std::vector<ModelInfo> &mi,
+              const nlch_sample *samples, int64_t n_samples, int prec, int algo, bool is_batch,
+              Batch **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<uint8_t> key;
+    append_bytes(key, dev);
+    append_bytes(key, prec);
+    append_bytes(key, algo & 0x1ff);
+    append_bytes(key, n_models);
+    append_bytes(key, n_samples);
+    for (int i = 0; i < n_models; ++i) append_bytes(key, models[i]);
+    const uint8_t *sp = reinterpret_cast<const uint8_t *>(samples);
+    key.insert(key.end(), sp, sp + sizeof(nlch_sample) * (size_t)n_samples);
+    for (size_t i = 0; i < g_batches.size(); ++i) {
+        if (g_batches[i]->key == key) {
+            std::unique_ptr<Batch> b = std::move(g_batches[i]);
+            g_batches.erase(g_batches.begin() + i);
+            g_batches.push_back(std::move(b));
+            *out = g_batches.back().get();
+            return NLCH_OK;
+        }
+    }
+
+    const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || prec == kF64;
+    std::unique_ptr<Batch> b(new Batch());
+    b->key = key;
+    b->device = dev;
+
+    // Geometry and weight tables.
+    std::vector<ModelGeo> geo(n_models);
+    std::vector<float> ewf;
+    std::vector<double> ewd;
+    for (int i = 0; i < n_models; ++i) {
+        ModelGeo &gm = geo[i];
+        std::memset(&gm, 0, sizeof(gm));
+        gm.n = models[i].n;
+        gm.m = mi[i].m;
+        gm.R2 = (int32_t)mi[i].R2;
+        gm.N = (int32_t)mi[i].N;
+        gm.kernel = models[i].kernel;
+        gm.e_off = (int64_t)ewd.size();
+        gm.ced = mi[i].ce_sep;
+        gm.cef = rne_f32(mi[i].ce_sep);
+        for (int k = 0; k <= mi[i].m; ++k) {
+            gm.gd[k] = mi[i].g[k];
+            gm.gf[k] = rne_f32(mi[i].g[k]);
+            gm.halfw[k] = mi[i].halfw[k];
+        }
+        for (double e : mi[i].e2) {
+            ewd.push_back(e);
+            ewf.push_back(rne_f32(e));
+        }
+    }
+    // Sample descriptors.
+    std::vector<SampleDesc> sd((size_t)n_samples);
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const nlch_sample &sm = samples[s];
+        Coef c;
+        char what[64];
+        snprintf(what, sizeof(what), "sample %lld", (long long)s);
+        int rc = sample_coef(models[sm.model], mi[sm.model], sm.c_F, sm.kernel_amp, c, what);
+        if (rc) return rc;
+        SampleDesc &d = sd[(size_t)s];
+        std::memset(&d, 0, sizeof(d));
+        d.offset = sm.offset;
+        d.model = sm.model;
+        d.n = models[sm.model].n;
+        d.a = c.a;
+        d.b = c.b;
+        d.af = rne_f32(c.a);
+        d.bf = rne_f32(c.b);
+    }
+    // Groups: per model, samples in batch order.
+    std::vector<std::vector<int32_t>> per_model(n_models);
+    for (int64_t s = 0; s < n_samples; ++s) per_model[samples[s].model].push_back((int32_t)s);
+    std::vector<int32_t> ids;
+    std::vector<size_t> id_off;
+    const int base = algo & 0xff;
+    for (int i = 0; i < n_models; ++i) {
+        if (per_model[i].empty()) continue;
+        int variant = 0;
+        int rc = choose_variant(base, prec, acc64, mi[i], models[i], is_batch, &variant);
+        if (rc) return rc;
+        Group g;
+        std::memset(&g, 0, sizeof(g));
+        g.nids = (int32_t)per_model[i].size();
+        g.n = models[i].n;
+        g.m = mi[i].m;
+        g.R2 = (int32_t)mi[i].R2;
+        g.kernel = models[i].kernel;
+        g.model = i;
+        id_off.push_back(ids.size());
+        ids.insert(ids.end(), per_model[i].begin(), per_model[i].end());
+        b->groups.push_back(g);
+        b->variant.push_back(variant);
+    }
+    // Upload (synchronous; once per signature).
+    HIP_TRY(hipMalloc(&b->geo.p, sizeof(ModelGeo) * geo.size()));
+    HIP_TRY(hipMemcpy(b->geo.p, geo.data(), sizeof(ModelGeo) * geo.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->ewf.p, sizeof(float) * ewf.size()));
+    HIP_TRY(hipMemcpy(b->ewf.p, ewf.data(), sizeof(float) * ewf.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->ewd.p, sizeof(double) * ewd.size()));
+    HIP_TRY(hipMemcpy(b->ewd.p, ewd.data(), sizeof(double) * ewd.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->sd.p, sizeof(SampleDesc) * sd.size()));
+    HIP_TRY(hipMemcpy(b->sd.p, sd.data(), sizeof(SampleDesc) * sd.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->ids.p, sizeof(int32_t) * ids.size()));
+    HIP_TRY(hipMemcpy(b->ids.p, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice));
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        Group &g = b->groups[gi];
+        g.geo = reinterpret_cast<const ModelGeo *>(b->geo.p) + g.model;
+        g.ewf = reinterpret_cast<const float *>(b->ewf.p);
+        g.ewd = reinterpret_cast<const double *>(b->ewd.p);
+        g.sd = reinterpret_cast<const SampleDesc *>(b->sd.p);
+        g.ids = reinterpret_cast<const int32_t *>(b->ids.p) + id_off[gi];
+    }
+    if (g_batches.size() >= kMaxBatches) g_batches.erase(g_batches.begin());
+    g_batches.push_back(std::move(b));
+    *out = g_batches.back().get();
+    return NLCH_OK;
+}
+
+hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
+                       void *out, hipStream_t s) {
+    if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s);
+    return launch_direct_step(prec, acc64, g, in, out, s);
+}
+
+// Enqueues a whole batch solve on stream s.
+int enqueue_solve(Batch &b, int prec, bool acc64, int nsteps, void *state, void *scratch,
+                  double *ooi, hipStream_t s) {
+    bool any_stream = false;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+        const Group &g = b.groups[gi];
+        if (b.variant[gi] == kResident) {
+            HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, s));
+        } else {
+            any_stream = true;
+        }
+    }
+    if (!any_stream) return NLCH_OK;
+    // Ping-pong: project into buf0 so that the last step lands in `state`.
+    void *buf0 = (nsteps % 2) ? scratch : state;
+    void *buf1 = (buf0 == state) ? scratch : state;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi)
+        if (b.variant[gi] != kResident) HIP_TRY(launch_project(prec, b.groups[gi], state, buf0, s));
+    void *cur = buf0, *nxt = buf1;
+    for (int k = 0; k < nsteps; ++k) {
+        for (size_t gi = 0; gi < b.groups.size(); ++gi)
+            if (b.variant[gi] != kResident)
+                HIP_TRY(launch_step(b.variant[gi], prec, acc64, b.groups[gi], cur, nxt, s));
+        std::swap(cur, nxt);
+    }
+    for (size_t gi = 0; gi < b.groups.size(); ++gi)
+        if (b.variant[gi] != kResident) HIP_TRY(launch_ooi(prec, b.groups[gi], state, ooi, 2, s));
+    return NLCH_OK;
+}
+
+int check_algo_flags(int32_t algo) {
+    const int32_t known = 0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_NOGRAPH | NLCH_ALGO_CHECK_FINITE;
+    if (algo & ~known) return fail(NLCH_EINVAL, "unknown algorithm flags 0x%x", algo & ~known);
+    const int base = algo & 0xff;
+    if (base < NLCH_ALGO_AUTO || base > NLCH_ALGO_RESIDENT)
+        return fail(NLCH_EINVAL, "unknown algorithm %d", base);
+    return NLCH_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------- ABI --
+
+extern "C" {
+
+int nlch_version(void) { return 1; }
+
+const char *nlch_last_error(void) { return g_last_error.c_str(); }
+
+int nlch_rowrun_supported(int64_t *r2_list, int32_t cap) {
+    if (cap < 0 || (cap > 0 && !r2_list)) return fail(NLCH_EINVAL, "bad output array");
+    return rowrun_r2_list(r2_list, cap);
+}
+
+int nlch_disc(int32_t n, double delta, int64_t *R2, int32_t *m, int64_t *N, int32_t *halfw,
+              int32_t cap) {
+    if (n <= 0) return fail(NLCH_EINVAL, "n must be > 0");
+    if (!std::isfinite(delta) || delta < 0.0 || delta * n > 1e6)
+        return fail(NLCH_EINVAL, "delta must be finite and >= 0");
+    const double r = delta * (double)n;
+    const int64_t r2 = (int64_t)std::floor(r * r + 1e-9);
+    const int64_t mm = isqrt64(r2);
+    if (halfw && cap < 2 * mm + 1) return fail(NLCH_EINVAL, "halfw needs %lld entries",
+                                                (long long)(2 * mm + 1));
+    int64_t cnt = 0;
+    for (int64_t dy = -mm; dy <= mm; ++dy) {
+        const int64_t w = isqrt64(r2 - dy * dy);
+        if (halfw) halfw[dy + mm] = (int32_t)w;
+        cnt += 2 * w + 1;
+    }
+    if (R2) *R2 = r2;
+    if (m) *m = (int32_t)mm;
+    if (N) *N = cnt;
+    return NLCH_OK;
+}
+
+int nlch_model_constants(const nlch_model *model, double *c_gamma_h, double *xi_h, double *c1) {
+    if (!model) return fail(NLCH_EINVAL, "model is NULL");
+    ModelInfo mi;
+    int rc = analyze_model(*model, mi, "model");
+    if (rc) return rc;
+    Coef c;
+    rc = sample_coef(*model, mi, model->c_F, model->kernel_amp, c, "model");
+    if (rc) return rc;
+    if (c_gamma_h) *c_gamma_h = c.c_gamma_h;
+    if (xi_h) *xi_h = c.xi_h;
+    if (c1) *c1 = c.c1;
+    return NLCH_OK;
+}
+
+int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const void *u_in,
+              void *u_out, double *ooi_out, void *hip_stream) {
+    if (!model) return fail(NLCH_EINVAL, "model is NULL");
+    if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
+        return fail(NLCH_EINVAL, "unknown precision %d", precision);
+    int rc = check_algo_flags(algo);
+    if (rc) return rc;
+    if ((algo & 0xff) == NLCH_ALGO_RESIDENT)
+        return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
+    if (!u_in || !u_out) return fail(NLCH_EINVAL, "state pointers must be non-NULL");
+    ModelInfo mi;
+    rc = analyze_model(*model, mi, "model");
+    if (rc) return rc;
+    const size_t bytes = prec_size(precision) * (size_t)model->n * model->n;
+    const char *pi = (const char *)u_in, *po = (const char *)u_out;
+    if (pi < po + bytes && po < pi + bytes)
+        return fail(NLCH_EINVAL, "u_in and u_out overlap (the stencil reads neighbours)");
+    nlch_sample smp;
+    std::memset(&smp, 0, sizeof(smp));
+    smp.model = 0;
+    smp.c_F = model->c_F;
+    smp.kernel_amp = model->kernel_amp;
+    smp.offset = 0;
+    Coef c;
+    rc = sample_coef(*model, mi, smp.c_F, smp.kernel_amp, c, "model");
+    if (rc) return rc;
+    {
+        int variant = 0;
+        rc = choose_variant(algo & 0xff, precision,
+                            (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64, mi, *model,
+                            false, &variant);
+        if (rc) return rc;
+    }
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *ctx = nullptr;
+    rc = dev_ctx(&ctx);
+    if (rc) return rc;
+    std::vector<ModelInfo> mis{mi};
+    Batch *b = nullptr;
+    rc = get_batch(model, 1, mis, &smp, 1, precision, algo & ~NLCH_ALGO_CHECK_FINITE, false, &b);
+    if (rc) return rc;
+    const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Group &g = b->groups[0];
+    HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
+    if (ooi_out) HIP_TRY(launch_ooi(precision, g, u_out, ooi_out, 2, s));
+    return NLCH_OK;
+}
+
+int nlch_solve_batch(const nlch_model *models, int32_t n_models, const nlch_sample *samples,
+                     int64_t n_samples, int32_t nsteps, int32_t precision, int32_t algo,
+                     void *state, void *scratch, double *ooi_out, void *hip_stream) {
+    if (!models || n_models < 1) return fail(NLCH_EINVAL, "need at least one model");
+    if (!samples || n_samples < 1) return fail(NLCH_EINVAL, "need at least one sample");
+    if (n_samples > (int64_t)1 << 30) return fail(NLCH_EINVAL, "too many samples");
+    if (nsteps < 0) return fail(NLCH_EINVAL, "nsteps must be >= 0");
+    if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
+        return fail(NLCH_EINVAL, "unknown precision %d", precision);
+    int rc = check_algo_flags(algo);
+    if (rc) return rc;
+    if (!state || !ooi_out) return fail(NLCH_EINVAL, "state and ooi_out must be non-NULL");
+    std::vector<ModelInfo> mi((size_t)n_models);
+    for (int i = 0; i < n_models; ++i) {
+        char what[48];
+        snprintf(what, sizeof(what), "model %d", i);
+        rc = analyze_model(models[i], mi[i], what);
+        if (rc) return rc;
+    }
+    // Samples: indices, parameters, non-overlapping states.
+    std::vector<std::pair<int64_t, int64_t>> extents((size_t)n_samples);
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const nlch_sample &sm = samples[s];
+        if (sm.model < 0 || sm.model >= n_models)
+            return fail(NLCH_EINVAL, "sample %lld: model index %d out of range", (long long)s,
+                        sm.model);
+        if (sm.reserved != 0)
+            return fail(NLCH_EINVAL, "sample %lld: reserved field must be 0", (long long)s);
+        if (!finite_pos(sm.c_F) || !finite_pos(sm.kernel_amp))
+            return fail(NLCH_EINVAL, "sample %lld: c_F and kernel_amp must be > 0", (long long)s);
+        if (sm.offset < 0) return fail(NLCH_EINVAL, "sample %lld: negative offset", (long long)s);
+        const int64_t nn = (int64_t)models[sm.model].n * models[sm.model].n;
+        extents[(size_t)s] = {sm.offset, sm.offset + nn};
+        Coef c;
+        char what[48];
+        snprintf(what, sizeof(what), "sample %lld", (long long)s);
+        rc = sample_coef(models[sm.model], mi[sm.model], sm.c_F, sm.kernel_amp, c, what);
+        if (rc) return rc;
+    }
+    std::sort(extents.begin(), extents.end());
+    for (size_t i = 1; i < extents.size(); ++i)
+        if (extents[i].first < extents[i - 1].second)
+            return fail(NLCH_EINVAL, "sample states overlap in the state buffer");
+    // Kernel variant per model (host decision, before any device work).
+    const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64;
+    std::vector<char> used((size_t)n_models, 0);
+    for (int64_t s = 0; s < n_samples; ++s) used[(size_t)samples[s].model] = 1;
+    bool need_scratch = false;
+    for (int i = 0; i < n_models; ++i) {
+        if (!used[(size_t)i]) continue;
+        int variant = 0;
+        rc = choose_variant(algo & 0xff, precision, acc64, mi[i], models[i], true, &variant);
+        if (rc) return rc;
+        need_scratch |= (variant != kResident);
+    }
+    if (need_scratch && !scratch)
+        return fail(NLCH_EINVAL, "scratch must be non-NULL unless every sample runs RESIDENT");
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *ctx = nullptr;
+    rc = dev_ctx(&ctx);
+    if (rc) return rc;
+    Batch *b = nullptr;
+    rc = get_batch(models, n_models, mi, samples, n_samples, precision, algo, true, &b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    if (algo & NLCH_ALGO_CHECK_FINITE) {
+        HIP_TRY(hipMemsetAsync(ctx->counter, 0, sizeof(unsigned int), s));
+        for (const Group &g : b->groups)
+            HIP_TRY(launch_count_nonfinite(precision, g, state, ctx->counter, s));
+        HIP_TRY(hipMemcpyAsync(ctx->counter_h, ctx->counter, sizeof(unsigned int),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*ctx->counter_h)
+            return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
+    }
+
+    if (algo & NLCH_ALGO_NOGRAPH)
+        return enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, s);
+
+    std::vector<uint8_t> gk;
+    append_bytes(gk, state);
+    append_bytes(gk, scratch);
+    append_bytes(gk, ooi_out);
+    append_bytes(gk, nsteps);
+    auto it = b->graphs.find(gk);
+    if (it == b->graphs.end()) {
+        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+        rc = enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, ctx->capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail(NLCH_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail(NLCH_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        it = b->graphs.emplace(gk, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s));
+    return NLCH_OK;
+}
+
+int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, const double *alpha,
+                  mfmc_result *out, void *hip_stream) {
+    if (K < 1 || K > NLCH_MFMC_MAX_K)
+        return fail(NLCH_EINVAL, "K must be in [1, %d]", NLCH_MFMC_MAX_K);
+    if (!m || !y_dev || !out) return fail(NLCH_EINVAL, "m, y_dev and out must be non-NULL");
+    if (m[0] < 2) return fail(NLCH_EINVAL, "m[0] must be >= 2");
+    for (int j = 1; j < K; ++j)
+        if (m[j] < m[j - 1]) return fail(NLCH_EINVAL, "sample counts must be non-decreasing");
+    for (int j = 0; j < K; ++j)
+        if (!y_dev[j]) return fail(NLCH_EINVAL, "y_dev[%d] is NULL", j);
+    if (alpha)
+        for (int j = 0; j + 1 < K; ++j)
+            if (!std::isfinite(alpha[j])) return fail(NLCH_EINVAL, "alpha[%d] not finite", j);
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *ctx = nullptr;
+    int rc = dev_ctx(&ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(launch_moments(K, y_dev, m, ctx->mom, s));
+    HIP_TRY(hipMemcpyAsync(ctx->mom_h, ctx->mom, sizeof(double) * 8 * K, hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memset(out, 0, sizeof(*out));
+    const double *mo = ctx->mom_h;
+    const double var1 = mo[2];
+    for (int j = 0; j < K; ++j) {
+        out->mean_mj[j] = mo[8 * j + 0];
+        out->mean_mjm1[j] = j > 0 ? mo[8 * j + 1] : NAN;
+        out->var[j] = mo[8 * j + 2];
+        const double cov = mo[8 * j + 3];
+        out->rho[j] = (var1 == 0.0 || out->var[j] == 0.0)
+                          ? 0.0
+                          : cov / std::sqrt(var1 * out->var[j]);
+    }
+    out->alpha[0] = 1.0;
+    for (int j = 1; j < K; ++j) {
+        if (alpha)
+            out->alpha[j] = alpha[j - 1];
+        else
+            out->alpha[j] = out->var[j] == 0.0
+                                ? 0.0
+                                : out->rho[j] * std::sqrt(var1) / std::sqrt(out->var[j]);
+    }
+    double q = out->mean_mj[0];
+    for (int j = 1; j < K; ++j) q += out->alpha[j] * (out->mean_mj[j] - out->mean_mjm1[j]);
+    out->q_mfmc = q;
+    out->q_mc = out->mean_mj[0];
+    return NLCH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the host runtime (nlch_api.cpp) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nlch {
+
+// Largest horizon in lattice units the kernels accept (m = floor(sqrt(R2))).
+constexpr int kMaxM = 48;
+
+enum Prec { kF64 = 0, kF32 = 1, kF16 = 2 };
+
+// Per-model geometry and kernel factors, resident in device memory.
+//   halfw[|dy|] = floor(sqrt(R2 - dy^2))      (row half-widths of the disc)
+//   gf/gd[k]    = exp(-k^2 h^2 / sigma^2)      (Gaussian), 1 (constant kernel)
+//   ce          = sum_{d in D} g(|dy|) g(|dx|) (unit-amplitude mass, separable)
+// The exact 2-D unit weights e(|dy|,|dx|) = exp(-h^2 |d|^2 / sigma^2) used by
+// the direct kernel live in a separate table at offset e_off, row-major
+// (m+1) x (m+1).
+struct ModelGeo {
+    int32_t n, m, R2, N;
+    int32_t kernel, pad0;
+    int64_t e_off;
+    double ced;
+    float cef, pad1;
+    float gf[kMaxM + 1];
+    double gd[kMaxM + 1];
+    int32_t halfw[kMaxM + 1];
+};
+
+// Per-sample update coefficients: with Lsum the unit-amplitude operator sum
+// sum_{d != 0} e_d (u - u_{+d}),  v = u + (a u - b Lsum),  u' = clamp(v).
+//   a = c1 c_F,  b = c1 h^2 amp,  c1 = tau beta1 / (1 + tau beta1 xi_h).
+struct SampleDesc {
+    int64_t offset;   // element offset of the sample's n x n state
+    int32_t model;
+    int32_t n;
+    double a, b;
+    float af, bf;
+    int64_t pad;
+};
+
+// One launch group: samples of one model, processed by one kernel variant.
+struct Group {
+    const ModelGeo *geo;    // device pointer to this model's geometry
+    const float *ewf;       // device pointer to the 2-D unit weight tables
+    const double *ewd;      //   (FP32 and FP64 copies, indexed from e_off)
+    const SampleDesc *sd;   // device pointer to all sample descriptors
+    const int32_t *ids;     // device pointer to this group's sample indices
+    int32_t nids;
+    int32_t n, m, R2;
+    int32_t kernel;
+    int32_t model;
+};
+
+// Kernel variants.
+enum Variant { kDirect = 1, kRowrun = 2, kResident = 3 };
+
+// Launch wrappers (return the launch status).  `acc64` selects FP64
+// accumulation for the F32/F16 storage types (always on for F64).
+hipError_t launch_project(int prec, const Group &g, const void *src, void *dst,
+                          hipStream_t s);
+hipError_t launch_count_nonfinite(int prec, const Group &g, const void *src,
+                                  unsigned int *counter, hipStream_t s);
+hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi,
+                      int per_sample_slots, hipStream_t s);
+hipError_t launch_direct_step(int prec, bool acc64, const Group &g,
+                              const void *in, void *out, hipStream_t s);
+bool rowrun_supported(int prec, bool acc64, int R2, int kernel);
+hipError_t launch_rowrun_step(int prec, bool acc64, const Group &g,
+                              const void *in, void *out, hipStream_t s);
+bool resident_supported(int prec, bool acc64, int R2, int kernel, int n);
+hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
+                           int nsteps, double *ooi, hipStream_t s);
+hipError_t launch_moments(int K, const double *const *y, const int64_t *m,
+                          double *out, hipStream_t s);
+
+// List of R2 values with compiled row-run kernels.
+int rowrun_r2_list(int64_t *out, int cap);
+
+}  // namespace nlch

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of ``libnlch.so`` (C ABI in ``include/nlch.h``).
+
+Functions carry the C names and only marshal arguments: device buffers may be
+torch tensors (their ``data_ptr()`` is passed) or raw integer addresses, and
+streams may be ``torch.cuda.Stream`` objects, raw ``hipStream_t`` integers or
+None (the null stream).  Every solver step runs inside the library's HIP
+kernels; there is no fallback path, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlch.so")
+
+NLCH_OK = 0
+NLCH_EINVAL = -1
+NLCH_EUNSUPPORTED = -2
+NLCH_EDEVICE = -3
+NLCH_ENOMEM = -4
+
+NLCH_KERNEL_CONSTANT = 0
+NLCH_KERNEL_GAUSSIAN = 1
+
+NLCH_F64 = 0
+NLCH_F32 = 1
+NLCH_F16_STORE = 2
+
+NLCH_ALGO_AUTO = 0
+NLCH_ALGO_DIRECT = 1
+NLCH_ALGO_ROWRUN = 2
+NLCH_ALGO_RESIDENT = 3
+NLCH_ALGO_ACC64 = 0x100
+NLCH_ALGO_NOGRAPH = 0x200
+NLCH_ALGO_CHECK_FINITE = 0x400
+
+NLCH_MFMC_MAX_K = 8
+
+PRECISIONS = {"f64": NLCH_F64, "f32": NLCH_F32, "f16": NLCH_F16_STORE}
+
+
+class nlch_model(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("kernel_amp", ctypes.c_double),
+                ("kernel_sigma", ctypes.c_double), ("c_F", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("tau", ctypes.c_double)]
+
+
+class nlch_sample(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("c_F", ctypes.c_double), ("kernel_amp", ctypes.c_double),
+                ("offset", ctypes.c_int64)]
+
+
+_K8 = ctypes.c_double * NLCH_MFMC_MAX_K
+
+
+class mfmc_result(ctypes.Structure):
+    _fields_ = [("q_mfmc", ctypes.c_double), ("q_mc", ctypes.c_double),
+                ("mean_mj", _K8), ("mean_mjm1", _K8), ("var", _K8),
+                ("rho", _K8), ("alpha", _K8)]
+
+
+class NlchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("nlch error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libnlch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnlch.so is not built (%s); run __graft_entry__.build()"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    pd = ctypes.POINTER(ctypes.c_double)
+    lib.nlch_disc.argtypes = [i32, ctypes.c_double, ctypes.POINTER(i64),
+                              ctypes.POINTER(i32), ctypes.POINTER(i64),
+                              ctypes.POINTER(i32), i32]
+    lib.nlch_disc.restype = ctypes.c_int
+    lib.nlch_model_constants.argtypes = [ctypes.POINTER(nlch_model), pd, pd, pd]
+    lib.nlch_model_constants.restype = ctypes.c_int
+    lib.nlch_step.argtypes = [ctypes.POINTER(nlch_model), i32, i32, vp, vp, vp, vp]
+    lib.nlch_step.restype = ctypes.c_int
+    lib.nlch_solve_batch.argtypes = [ctypes.POINTER(nlch_model), i32,
+                                     ctypes.POINTER(nlch_sample), i64, i32, i32,
+                                     i32, vp, vp, vp, vp]
+    lib.nlch_solve_batch.restype = ctypes.c_int
+    lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                  pd, ctypes.POINTER(mfmc_result), vp]
+    lib.mfmc_estimate.restype = ctypes.c_int
+    lib.nlch_rowrun_supported.argtypes = [ctypes.POINTER(i64), i32]
+    lib.nlch_rowrun_supported.restype = ctypes.c_int
+    lib.nlch_last_error.argtypes = []
+    lib.nlch_last_error.restype = ctypes.c_char_p
+    lib.nlch_version.argtypes = []
+    lib.nlch_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != NLCH_OK:
+        raise NlchError(rc, nlch_last_error())
+
+
+def _ptr(buf):
+    if buf is None:
+        return None
+    if isinstance(buf, int):
+        return buf
+    return buf.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def nlch_last_error() -> str:
+    return load().nlch_last_error().decode()
+
+
+def nlch_version() -> int:
+    return load().nlch_version()
+
+
+def nlch_rowrun_supported():
+    lib = load()
+    buf = (ctypes.c_int64 * 64)()
+    cnt = lib.nlch_rowrun_supported(buf, 64)
+    _check(0 if cnt >= 0 else cnt)
+    return [buf[i] for i in range(min(cnt, 64))]
+
+
+def nlch_disc(n: int, delta: float):
+    """(R2, m, N, halfw list for dy = -m..m)."""
+    lib = load()
+    R2 = ctypes.c_int64()
+    m = ctypes.c_int32()
+    N = ctypes.c_int64()
+    _check(lib.nlch_disc(n, delta, ctypes.byref(R2), ctypes.byref(m), ctypes.byref(N),
+                         None, 0))
+    hw = (ctypes.c_int32 * (2 * m.value + 1))()
+    _check(lib.nlch_disc(n, delta, None, None, None, hw, 2 * m.value + 1))
+    return R2.value, m.value, N.value, list(hw)
+
+
+def make_model(n, delta, kernel, amp, sigma=0.0, c_F=1.0, beta1=1.0, beta2=0.0,
+               tau=0.01) -> nlch_model:
+    return nlch_model(int(n), int(kernel), float(delta), float(amp), float(sigma),
+                      float(c_F), float(beta1), float(beta2), float(tau))
+
+
+def nlch_model_constants(model: nlch_model):
+    c = ctypes.c_double()
+    xi = ctypes.c_double()
+    c1 = ctypes.c_double()
+    _check(load().nlch_model_constants(ctypes.byref(model), ctypes.byref(c),
+                                       ctypes.byref(xi), ctypes.byref(c1)))
+    return c.value, xi.value, c1.value
+
+
+def nlch_step(model: nlch_model, precision: int, algo: int, u_in, u_out,
+              ooi_out=None, stream=None) -> None:
+    _check(load().nlch_step(ctypes.byref(model), precision, algo, _ptr(u_in),
+                            _ptr(u_out), _ptr(ooi_out), _stream(stream)))
+
+
+def nlch_solve_batch(models, samples, nsteps: int, precision: int, algo: int, state,
+                     scratch, ooi_out, stream=None) -> None:
+    """models: sequence of nlch_model (or a ctypes array); samples: sequence of
+    nlch_sample (or a ctypes array)."""
+    if not isinstance(models, ctypes.Array):
+        models = (nlch_model * len(models))(*models)
+    if not isinstance(samples, ctypes.Array):
+        samples = (nlch_sample * len(samples))(*samples)
+    _check(load().nlch_solve_batch(models, len(models), samples, len(samples),
+                                   int(nsteps), precision, algo, _ptr(state),
+                                   _ptr(scratch), _ptr(ooi_out), _stream(stream)))
+
+
+def mfmc_estimate(ys, m, alpha=None, stream=None) -> dict:
+    """ys: K device arrays (float64) of model outputs; m: K sample counts."""
+    K = len(ys)
+    mm = (ctypes.c_int64 * K)(*[int(v) for v in m])
+    yp = (ctypes.c_void_p * K)(*[_ptr(y) for y in ys])
+    al = None
+    if alpha is not None:
+        al = (ctypes.c_double * max(1, K - 1))(*[float(a) for a in alpha])
+    res = mfmc_result()
+    _check(load().mfmc_estimate(K, mm, yp, al, ctypes.byref(res), _stream(stream)))
+    return {
+        "q_mfmc": res.q_mfmc,
+        "q_mc": res.q_mc,
+        "mean_mj": list(res.mean_mj[:K]),
+        "mean_mjm1": list(res.mean_mjm1[:K]),
+        "var": list(res.var[:K]),
+        "rho": list(res.rho[:K]),
+        "alpha": list(res.alpha[:K]),
+    }
+
+
+# ----------------------------------------------------------- marshalling --
+
+def structs_for(workload):
+    """nlch_model / nlch_sample arrays for a synth.Workload, states packed
+    contiguously in sample order.  Returns (models, samples, total_elements)."""
+    models = (nlch_model * len(workload.models))(*[
+        make_model(m.n, m.delta, m.kernel, m.amp, m.sigma, m.c_F, m.beta1, m.beta2,
+                   m.tau) for m in workload.models])
+    samples = (nlch_sample * len(workload.samples))()
+    off = 0
+    for i, s in enumerate(workload.samples):
+        n = workload.models[s.model].n
+        samples[i] = nlch_sample(s.model, 0, float(s.c_F), float(s.amp), off)
+        off += n * n
+    return models, samples, off

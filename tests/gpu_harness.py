@@ -1,0 +1,77 @@
+"""Helpers shared by the GPU parity tests and the benchmark: device buffers for
+a synthetic workload, and the matching FP64 oracle runs.
+
+The oracle is always fed exactly the values the GPU starts from (the synthetic
+FP64 initial data rounded to the state type), so a comparison isolates the
+kernels' arithmetic.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2310_10750_amd import nlch, synth
+
+TORCH_DTYPE = {"f64": "float64", "f32": "float32", "f16": "float16"}
+NP_DTYPE = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+
+
+def rounded_initial(w, s, prec):
+    """Initial datum of sample s rounded (RNE) to the state type, as FP64."""
+    return synth.initial_state(w, s).astype(NP_DTYPE[prec]).astype(np.float64)
+
+
+class DeviceBatch:
+    """State / scratch / OoI buffers of a workload on cuda:0."""
+
+    def __init__(self, w, prec=None, device="cuda:0", samples=None):
+        import torch
+        self.w = w
+        self.prec = prec or w.precision
+        self.models, self.samples, self.total = nlch.structs_for(w)
+        self.dtype = getattr(torch, TORCH_DTYPE[self.prec])
+        host = np.empty(self.total, dtype=NP_DTYPE[self.prec])
+        for i, s in enumerate(w.samples):
+            n = w.models[s.model].n
+            off = self.samples[i].offset
+            host[off:off + n * n] = synth.initial_state(w, s).astype(
+                NP_DTYPE[self.prec]).reshape(-1)
+        self.host0 = host
+        self.state = torch.from_numpy(host).to(device)
+        self.init = self.state.clone()
+        self.scratch = torch.empty_like(self.state)
+        self.ooi = torch.zeros(2 * len(w.samples), dtype=torch.float64, device=device)
+
+    def reset(self):
+        self.state.copy_(self.init)
+
+    def solve(self, algo=nlch.NLCH_ALGO_AUTO, nsteps=None, stream=None):
+        nlch.nlch_solve_batch(self.models, self.samples,
+                              self.w.nsteps if nsteps is None else nsteps,
+                              nlch.PRECISIONS[self.prec], algo, self.state,
+                              self.scratch, self.ooi, stream)
+
+    def sample_state(self, i):
+        n = self.w.models[self.w.samples[i].model].n
+        off = self.samples[i].offset
+        return self.state[off:off + n * n].double().cpu().numpy().reshape(n, n)
+
+    def ooi_host(self):
+        return self.ooi.cpu().numpy().reshape(-1, 2)
+
+
+def oracle_samples(orc, w, idx, prec, nsteps=None):
+    """FP64 oracle trajectories of the listed samples (grouped by model)."""
+    nsteps = w.nsteps if nsteps is None else nsteps
+    out = {}
+    by_model = {}
+    for i in idx:
+        by_model.setdefault(w.samples[i].model, []).append(i)
+    for mi, ids in by_model.items():
+        m = w.models[mi]
+        u0 = np.stack([rounded_initial(w, w.samples[i], prec) for i in ids])
+        U, mean, f1 = orc.solve_many(u0, nsteps, m.n, m.delta, m.kernel, m.sigma,
+                                     m.beta1, m.tau, [w.samples[i].c_F for i in ids],
+                                     [w.samples[i].amp for i in ids])
+        for k, i in enumerate(ids):
+            out[i] = (U[k], mean[k], f1[k])
+    return out

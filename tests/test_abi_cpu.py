@@ -1,0 +1,159 @@
+"""C-ABI checks that need no GPU: the library loads and exports every function
+declared in include/nlch.h, host-side tables agree bit-exactly with the oracle,
+and invalid arguments are rejected before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_10750_amd import nlch, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "nlch.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_library_exports_every_declared_function():
+    lib = nlch.load()
+    names = _declared_functions()
+    assert {"nlch_step", "nlch_solve_batch", "mfmc_estimate", "nlch_last_error",
+            "nlch_disc", "nlch_model_constants", "nlch_rowrun_supported",
+            "nlch_version"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert nlch.nlch_version() >= 1
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(nlch.nlch_model) == 64
+    assert ctypes.sizeof(nlch.nlch_sample) == 32
+    assert ctypes.sizeof(nlch.mfmc_result) == 8 * (2 + 5 * nlch.NLCH_MFMC_MAX_K)
+
+
+@pytest.mark.parametrize("n,delta", [(64, 4 / 64), (88, 0.1875), (128, 0.25),
+                                     (64, 0.125), (512, 16 / 512), (40, 0.1),
+                                     (30, 0.1), (2048, 32 / 2048), (1024, 1 / 32),
+                                     (64, 1 / 32), (17, 0.0), (200, 0.0371)])
+def test_disc_tables_bit_exact_with_oracle(orc, n, delta):
+    R2, m, N, hw = nlch.nlch_disc(n, delta)
+    oR2, om, oN, ohw = orc.disc(n, delta)
+    assert (R2, m, N) == (oR2, om, oN)
+    assert hw == ohw.tolist()
+
+
+def test_rowrun_r2_list_covers_recipes():
+    r2 = set(nlch.nlch_rowrun_supported())
+    for name in ("C1", "C2", "C3", "C5"):
+        w = synth.workload(name, n_samples=1, nsteps=1)
+        m = w.models[0]
+        assert nlch.nlch_disc(m.n, m.delta)[0] in r2
+    for m in synth.workload("C4", n_samples=4, nsteps=1).models:
+        assert nlch.nlch_disc(m.n, m.delta)[0] in r2
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_model_constants_match_oracle(orc, kind):
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    if kind == 0:
+        amp = synth.constant_amp(128, 8, 1.0253)
+    for n, delta in [(128, 0.25), (88, 0.1875), (64, 0.125), (128, 8 / 128)]:
+        md = nlch.make_model(n, delta, kind, amp, sigma, c_F=1.0, tau=0.01)
+        c, xi, c1 = nlch.nlch_model_constants(md)
+        oc, oxi, _ = orc.constants(n, delta, kind, amp, sigma, 1.0)
+        assert abs(c - oc) <= 1e-13 * oc
+        assert abs(xi - oxi) <= 1e-13 * max(1.0, oc)
+        assert abs(c1 - 0.01 / (1 + 0.01 * oxi)) <= 1e-14 * c1
+
+
+def _good_model():
+    return nlch.make_model(32, 3 / 32, 0, 1.0, 0.0, 1.0, 1.0, 0.0, 0.01)
+
+
+def _err(fn, *a):
+    with pytest.raises(nlch.NlchError) as e:
+        fn(*a)
+    return e.value.code
+
+
+def test_model_validation_errors():
+    bad = [dict(n=2), dict(kernel=3), dict(delta=-1.0), dict(delta=float("nan")),
+           dict(kernel_amp=0.0), dict(kernel=1, kernel_sigma=0.0), dict(c_F=0.0),
+           dict(c_F=float("inf")), dict(beta1=0.0), dict(tau=0.0), dict(tau=-1.0),
+           dict(delta=16 / 32), dict(c_F=1e6)]
+    for kw in bad:
+        md = _good_model()
+        for k, v in kw.items():
+            setattr(md, k, v)
+        assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EINVAL, kw
+    md = _good_model()
+    md.beta2 = 0.05
+    assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EUNSUPPORTED
+    md = _good_model()
+    md.n, md.delta = 256, 60 / 256
+    assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EUNSUPPORTED
+    assert "beta2" in nlch.nlch_last_error() or "horizon" in nlch.nlch_last_error()
+
+
+def test_step_argument_errors():
+    md = _good_model()
+    E = nlch.NLCH_EINVAL
+    assert _err(nlch.nlch_step, md, 7, 0, 4096, 8192) == E
+    assert _err(nlch.nlch_step, md, 1, 0x800, 4096, 8192) == E
+    assert _err(nlch.nlch_step, md, 1, nlch.NLCH_ALGO_RESIDENT, 4096, 8192) == E
+    assert _err(nlch.nlch_step, md, 1, 0, 4096, 4096) == E           # aliasing
+    assert _err(nlch.nlch_step, md, 1, 0, 4096, 4096 + 100) == E     # overlap
+    assert _err(nlch.nlch_step, md, 1, 0, None, 8192) == E
+    md.beta2 = 0.1
+    assert _err(nlch.nlch_step, md, 1, 0, 4096, 1 << 20) == nlch.NLCH_EUNSUPPORTED
+
+
+def test_solve_batch_argument_errors():
+    md = _good_model()
+    nn = 32 * 32
+    S = [nlch.nlch_sample(0, 0, 1.0, 1.0, 0), nlch.nlch_sample(0, 0, 1.0, 1.0, nn)]
+    E = nlch.NLCH_EINVAL
+    big = 1 << 30
+    f = nlch.nlch_solve_batch
+    assert _err(f, [md], S, -1, 1, 0, big, big * 2, big * 3) == E
+    assert _err(f, [md], S, 5, 3, 0, big, big * 2, big * 3) == E
+    assert _err(f, [md], S, 5, 1, 0, None, big * 2, big * 3) == E
+    assert _err(f, [md], S, 5, 1, 0, big, big * 2, None) == E
+    overl = [nlch.nlch_sample(0, 0, 1.0, 1.0, 0), nlch.nlch_sample(0, 0, 1.0, 1.0, nn - 1)]
+    assert _err(f, [md], overl, 5, 1, 0, big, big * 2, big * 3) == E
+    badidx = [nlch.nlch_sample(1, 0, 1.0, 1.0, 0)]
+    assert _err(f, [md], badidx, 5, 1, 0, big, big * 2, big * 3) == E
+    badres = [nlch.nlch_sample(0, 7, 1.0, 1.0, 0)]
+    assert _err(f, [md], badres, 5, 1, 0, big, big * 2, big * 3) == E
+    badcf = [nlch.nlch_sample(0, 0, float("nan"), 1.0, 0)]
+    assert _err(f, [md], badcf, 5, 1, 0, big, big * 2, big * 3) == E
+    # per-sample stability condition 1 + tau beta1 xi > 0
+    unstable = [nlch.nlch_sample(0, 0, 1e4, 1.0, 0)]
+    assert _err(f, [md], unstable, 5, 1, 0, big, big * 2, big * 3) == E
+    # streaming variant needs scratch
+    assert _err(f, [md], S, 5, 1, nlch.NLCH_ALGO_DIRECT, big, None, big * 3) == E
+    # RESIDENT for a lattice that does not fit
+    big_md = nlch.make_model(512, 16 / 512, 0, 1.0, tau=0.01)
+    assert _err(f, [big_md], [nlch.nlch_sample(0, 0, 1.0, 1.0, 0)], 5, 1,
+                nlch.NLCH_ALGO_RESIDENT, big, big * 2, big * 3) == nlch.NLCH_EUNSUPPORTED
+    # ROWRUN for a horizon without a compiled kernel
+    odd = nlch.make_model(64, math.sqrt(7) / 64, 0, 1.0, tau=0.01)
+    assert _err(f, [odd], [nlch.nlch_sample(0, 0, 1.0, 1.0, 0)], 5, 1,
+                nlch.NLCH_ALGO_ROWRUN, big, big * 2, big * 3) == nlch.NLCH_EUNSUPPORTED
+
+
+def test_mfmc_argument_errors():
+    f = nlch.mfmc_estimate
+    E = nlch.NLCH_EINVAL
+    assert _err(f, [4096] * 9, [2] * 9) == E
+    assert _err(f, [4096, 8192], [1, 4]) == E
+    assert _err(f, [4096, 8192], [5, 4]) == E
+    assert _err(f, [4096, None], [2, 4]) == E
+    assert _err(f, [4096, 8192], [2, 4], [float("nan")]) == E
