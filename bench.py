@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched solve on one MI355X.
+
+One benchmark step is one pass of the whole path over one batch: reset the
+state buffer to the initial data (a device-to-device copy, inputs already in
+HBM), the batched solve (initial projection, every time step with the
+obstacle-constrained update, per-sample FP64 output of interest), and the FP64
+Monte Carlo moments of the outputs.  Default workload: 4096 samples of a
+128 x 128 periodic lattice, horizon 8h (197-point disc), constant kernel,
+per-sample c_F, 500 steps, FP32 state and arithmetic.
+
+Prints one JSON line on stdout (diagnostics go to stderr), with
+  roofline     -- the dominant kernel's algorithmic work rate against its bound,
+                  timed live with HIP events on the stream it runs on;
+  cpu_baseline -- the FP64 CPU oracle timed on a bounded sample of the same
+                  workload on the host cores (and the OoI error against it);
+  fp64_one_sample -- the same workload's throughput in FP64 with one sample per
+                  call and one launch per step (no graph) on the same GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("site-steps/s & HBM/LDS GB/s: batched FP32 vs 1-sample FP64, "
+          "OoI err stated")
+# VALU lane-operation issue rate of MI355X without packed FP32 instructions:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP32 add/mul/FMA per lane-op).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources, to tell whether stored counter data still
+    describe the current kernels."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2310_10750_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_ops(m: int, kernel: int) -> int:
+    """VALU lane-operations per site-step of the row-run evaluation:
+    2m window adds + (2m+1) accumulation adds + 6 for the update and clamp
+    (constant kernel); the Gaussian adds m + (2m+1) weight multiplies."""
+    ops = 2 * m + (2 * m + 1) + 6
+    if kernel == 1:
+        ops += m + (2 * m + 1)
+    return ops
+
+
+def stored_traffic(kernel_name: str):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    if it was measured on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    e = d.get(kernel_name)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--algo", type=int, default=0)
+    ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--fp64-samples", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU only: every box of this pool has one "
+              "MI355X, and the solver runs no multi-GPU path (samples would shard "
+              "by sample index with one FP64 all-reduce of the moment sums).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_10750_amd import nlch, synth
+    if not os.path.exists(nlch.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload)
+    prec = args.precision or w.precision
+    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[prec]
+    ndt = {"f64": np.float64, "f32": np.float32, "f16": np.float16}[prec]
+    models, samples, total = nlch.structs_for(w)
+    S = len(w.samples)
+    site_steps = w.site_steps()
+    log("workload %s: %d samples, %d site-steps per solve" % (w.name, S, site_steps))
+
+    t0 = time.time()
+    host = np.empty(total, dtype=ndt)
+    for i, s in enumerate(w.samples):
+        n = w.models[s.model].n
+        off = samples[i].offset
+        host[off:off + n * n] = synth.initial_state(w, s).astype(ndt).reshape(-1)
+    init = torch.from_numpy(host).to(dev)
+    state = torch.empty_like(init)
+    scratch = torch.empty_like(init)
+    ooi = torch.zeros(2 * S, dtype=torch.float64, device=dev)
+    log("inputs generated in %.1fs" % (time.time() - t0))
+
+    stream = torch.cuda.Stream(device=dev)
+    precision = nlch.PRECISIONS[prec]
+    level_counts = w.level_counts or [S]
+    # MFMC moments: levels are contiguous in sample order, HF first.
+    level_ptrs, off = [], 0
+    for c in level_counts:
+        level_ptrs.append(ooi.data_ptr() + 8 * (2 * off + 1))
+        off += c
+
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+
+    def one_step(i=None):
+        with torch.cuda.stream(stream):
+            state.copy_(init)
+            if i is not None:
+                ev_s[i].record(stream)
+            nlch.nlch_solve_batch(models, samples, w.nsteps, precision, args.algo, state,
+                                  scratch, ooi, stream)
+            if i is not None:
+                ev_e[i].record(stream)
+        return nlch.mfmc_estimate(level_ptrs, level_counts, stream=stream, y_stride=2)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        est = one_step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t_start
+    ms_per_step = 1e3 * dt / max(1, args.steps)
+    value = site_steps / (dt / max(1, args.steps))
+    solve_ms = float(np.mean([ev_s[i].elapsed_time(ev_e[i]) for i in range(args.steps)]))
+    log("%.3f ms/step, solve %.3f ms, %.3e site-steps/s" % (ms_per_step, solve_ms, value))
+
+    # Dominant kernel: with every sample LDS-resident the solve is one launch.
+    m0 = w.models[0]
+    R2, mdisc, N, _ = nlch.nlch_disc(m0.n, m0.delta)
+    resident = all(mm.n <= 128 for mm in w.models) and args.algo in (0, 3)
+    kname = "k_resident" if resident else "k_rowrun"
+    ops = sum(algorithmic_ops(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
+                              w.models[s.model].kernel) * w.models[s.model].n ** 2
+              for s in w.samples) * w.nsteps
+    achieved = ops / (solve_ms * 1e-3) / 1e12
+    traffic = stored_traffic(kname)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": traffic, "kernel": kname,
+                "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel)}
+    state_bytes = total * np.dtype(ndt).itemsize
+    hbm_gbs = 2 * state_bytes / (solve_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "%s: %s" % (w.name, w.description), "samples": S,
+                   "n": [mm.n for mm in w.models], "R2": R2, "disc_points": N,
+                   "time_steps": w.nsteps, "precision": prec, "algo": args.algo},
+        "roofline": roofline,
+        "hbm_state_gbs": round(hbm_gbs, 1),
+        "mc_estimate": {"q_mc": est["q_mc"], "var": est["var"][0]},
+    }
+
+    # FP64, one sample per call, one launch per step, no graph.
+    if not args.no_fp64_baseline:
+        k = min(args.fp64_samples, S)
+        mods = (nlch.nlch_model * len(w.models))(*models)
+        u64 = [torch.from_numpy(synth.initial_state(w, w.samples[i]).reshape(-1)).to(dev)
+               for i in range(k)]
+        scr = torch.empty_like(u64[0])
+        o64 = torch.zeros(2, dtype=torch.float64, device=dev)
+        algo64 = nlch.NLCH_ALGO_DIRECT | nlch.NLCH_ALGO_NOGRAPH
+        one = lambda i: nlch.nlch_solve_batch(
+            mods, [nlch.nlch_sample(samples[i].model, 0, samples[i].c_F,
+                                    samples[i].kernel_amp, 0)],
+            w.nsteps, nlch.NLCH_F64, algo64, u64[i], scr, o64, stream)
+        one(0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(k):
+            one(i)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t
+        ss64 = sum(w.models[w.samples[i].model].n ** 2 for i in range(k)) * w.nsteps
+        v64 = ss64 / t64
+        out["fp64_one_sample"] = {"value": v64, "unit": "site-steps/s", "samples": k,
+                                  "algo": "direct, 1 launch per step, no graph",
+                                  "speedup": value / v64}
+        log("fp64 one-sample: %.3e site-steps/s, speedup %.1fx" % (v64, value / v64))
+
+    # CPU oracle on a bounded sample (also the OoI error statement).
+    if not args.no_cpu_baseline:
+        import oracle
+        k = min(args.cpu_samples, S)
+        idx = list(range(k))
+        by_model = {}
+        for i in idx:
+            by_model.setdefault(w.samples[i].model, []).append(i)
+        o = ooi.view(-1, 2).cpu().numpy()
+        rel, tcpu, sscpu = [], 0.0, 0
+        for mi, ids in by_model.items():
+            mm = w.models[mi]
+            u0 = np.stack([synth.initial_state(w, w.samples[i]).astype(ndt).astype(np.float64)
+                           for i in ids])
+            t = time.perf_counter()
+            _, _, f1 = oracle.solve_many(u0, w.nsteps, mm.n, mm.delta, mm.kernel, mm.sigma,
+                                         mm.beta1, mm.tau, [w.samples[i].c_F for i in ids],
+                                         [w.samples[i].amp for i in ids], want_states=False)
+            tcpu += time.perf_counter() - t
+            sscpu += len(ids) * mm.n ** 2 * w.nsteps
+            for j, i in enumerate(ids):
+                rel.append(abs(o[i, 1] - f1[j]) / abs(f1[j]))
+        out["cpu_baseline"] = {"value": sscpu / tcpu, "unit": "site-steps/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": "%d of %d samples, all %d steps (%.1f s)"
+                                         % (k, S, w.nsteps, tcpu)}
+        out["ooi_rel_err"] = {"max": max(rel), "samples": k, "vs": "FP64 CPU oracle"}
+        log("cpu oracle %.3e site-steps/s on %d threads; max OoI rel err %.2e"
+            % (sscpu / tcpu, oracle.threads(), max(rel)))
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

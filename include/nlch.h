@@ -157,9 +157,11 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models,
                      void *hip_stream);
 
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
- * y_dev[j]: device array of at least m[j] doubles, y_dev[j][i] the output of
- * model j+1 for parameter draw i (draws shared across models: model j+1 uses
- * draws 0..m[j]-1).  m: host array, non-decreasing, m[0] >= 2.
+ * y_dev[j]: device pointer to the outputs of model j+1, the output for
+ * parameter draw i at y_dev[j][i * y_stride] for i < m[j] (draws shared
+ * across models: model j+1 uses draws 0..m[j]-1).  y_stride >= 1; pass 2
+ * and &ooi_out[2*s0 + 1] to read the f_1 values of nlch_solve_batch output
+ * in place.  m: host array, non-decreasing, m[0] >= 2.
  * alpha: NULL (estimate alpha_j = rho_{1j} sigma_1 / sigma_j, eq. alpha, from
  * the first m[0] shared draws; zero-variance models get alpha = 0) or K-1 host
  * values for models 2..K.  Moments are accumulated in FP64 on the device
@@ -167,10 +169,12 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models,
  * Q_MFMC = mean_1(m_1) + sum_j alpha_j (mean_j(m_j) - mean_j(m_{j-1}))
  * (eq. MFMC_estimator). */
 int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev,
-                  const double *alpha, mfmc_result *out, void *hip_stream);
+                  int64_t y_stride, const double *alpha, mfmc_result *out,
+                  void *hip_stream);
 
-/* Largest radius-squared values R2 for which the ROWRUN / RESIDENT kernels are
- * compiled: writes up to cap values into r2_list and returns their count. */
+/* The disc sizes R2 for which ROWRUN kernels are compiled (RESIDENT uses the
+ * subset with m <= 8): writes up to cap values into r2_list and returns the
+ * total count. */
 int nlch_rowrun_supported(int64_t *r2_list, int32_t cap);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */

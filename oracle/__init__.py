@@ -73,6 +73,8 @@ def _load():
     lib.orc_solve_many.argtypes = [i32, f64, i32, f64, f64, f64, i32, i64, pd,
                                    pd, pd, pd, pd]
     lib.orc_solve_many.restype = i32
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = i32
     _lib = lib
     return lib
 
@@ -90,6 +92,11 @@ def _f64(a, shape=None):
 
 class OracleError(RuntimeError):
     pass
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().orc_threads()
 
 
 def disc(n: int, delta: float):

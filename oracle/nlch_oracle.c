@@ -39,6 +39,7 @@
  * Build: gcc -O2 -fopenmp -shared -fPIC nlch_oracle.c -o liboracle.so -lm
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -401,3 +402,6 @@ int orc_solve_many(int n, double delta, int kind, double sigma, double beta1,
     }
     return bad ? -1 : 0;
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+int orc_threads(void) { return omp_get_max_threads(); }

@@ -13,6 +13,7 @@ namespace {
 struct MomArgs {
     const double *y[8];
     int64_t m[8];
+    int64_t stride;
     int K;
 };
 
@@ -24,13 +25,14 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs a, double *__restrict__
     const int64_t m0 = a.m[0], mj = a.m[j], mjm1 = j > 0 ? a.m[j - 1] : 0;
 
     double s_mj = 0.0, s_mjm1 = 0.0, s0j = 0.0, s01 = 0.0;
+    const int64_t st = a.stride;
     for (int64_t i = threadIdx.x; i < mj; i += 256) {
-        const double v = yj[i];
+        const double v = yj[i * st];
         s_mj += v;
         if (i < mjm1) s_mjm1 += v;
         if (i < m0) s0j += v;
     }
-    for (int64_t i = threadIdx.x; i < m0; i += 256) s01 += y1[i];
+    for (int64_t i = threadIdx.x; i < m0; i += 256) s01 += y1[i * st];
     s_mj = block_sum(s_mj, red);
     s_mjm1 = block_sum(s_mjm1, red);
     s0j = block_sum(s0j, red);
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs a, double *__restrict__
 
     double sv = 0.0, sc = 0.0;
     for (int64_t i = threadIdx.x; i < m0; i += 256) {
-        const double dj = yj[i] - mean0j, d1 = y1[i] - mean01;
+        const double dj = yj[i * st] - mean0j, d1 = y1[i * st] - mean01;
         sv += dj * dj;
         sc += d1 * dj;
     }
@@ -57,9 +59,10 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs a, double *__restrict__
 
 }  // namespace
 
-hipError_t launch_moments(int K, const double *const *y, const int64_t *m, double *out,
-                          hipStream_t s) {
+hipError_t launch_moments(int K, const double *const *y, const int64_t *m, int64_t stride,
+                          double *out, hipStream_t s) {
     MomArgs a{};
+    a.stride = stride;
     for (int j = 0; j < K; ++j) {
         a.y[j] = y[j];
         a.m[j] = m[j];

@@ -64,7 +64,7 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
     const int tpb = ((g.n + R - 1) / R + 63) / 64 * 64;
     const int nbands = (g.n + B - 1) / B;
     const int threads = tpb * nbands;
-    const size_t lds = (size_t)g.n * (g.n + 2 * M) * sizeof(TS);
+    const size_t lds = (size_t)g.n * resident_row_stride(g.n, M) * sizeof(TS);
     if (threads > 512 || lds > kLdsBytes - 1024) return hipErrorInvalidValue;
     auto go = [&](auto f) {
         static bool attr = false;
@@ -99,9 +99,10 @@ bool resident_has_typed(int R2, int n) {
     if (R2 == v) in_list = true;
     NLCH_RESIDENT_R2_LIST(NLCH_X)
 #undef NLCH_X
-    if (!in_list || n > 128) return false;
+    // 16 <= n keeps the band walk within two periods of the torus
+    if (!in_list || n > 128 || n < 16) return false;
     const int M = cisqrt(R2);
-    return (size_t)n * (n + 2 * M) * sizeof(TS) <= kLdsBytes - 1024;
+    return (size_t)n * resident_row_stride(n, M) * sizeof(TS) <= kLdsBytes - 1024;
 }
 
 template <class TS, class TA>

@@ -68,6 +68,27 @@ struct Disc {
     static constexpr CArr<int, M + 2> start = make_start();
 };
 
+// Loads win[0..WIN) = p[0..WIN) as TA, in pairs when the caller guarantees
+// that p is aligned to two elements (halves the LDS instructions and avoids
+// the bank conflicts of lane-strided 4-byte reads).
+template <int WIN, bool PAIRS, class TS, class TA>
+__device__ __forceinline__ void load_window(const TS *p, TA *win) {
+    if constexpr (PAIRS && sizeof(TS) >= 4) {
+        struct alignas(2 * sizeof(TS)) Pair { TS v[2]; };
+        const Pair *pp = reinterpret_cast<const Pair *>(p);
+#pragma unroll
+        for (int j = 0; j < WIN / 2; ++j) {
+            const Pair t = pp[j];
+            win[2 * j] = to_acc<TA>(t.v[0]);
+            win[2 * j + 1] = to_acc<TA>(t.v[1]);
+        }
+        if constexpr (WIN % 2) win[WIN - 1] = to_acc<TA>(p[WIN - 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) win[j] = to_acc<TA>(p[j]);
+    }
+}
+
 template <int B, int E, class F>
 __device__ __forceinline__ void sfor(F &&f) {
     if constexpr (B < E) {
@@ -162,8 +183,8 @@ __global__ __launch_bounds__(NW * 64) void k_rowrun(
             if (p < rows) {
                 const TS *rp = tile + (rowbase + p) * TW + c0;
                 TA win[WIN];
-#pragma unroll
-                for (int j = 0; j < WIN; ++j) win[j] = to_acc<TA>(rp[j]);
+                // TW and c0 are even when R is even
+                load_window<WIN, (R % 2 == 0)>(rp, win);
 #pragma unroll
                 for (int c = 0; c < R; ++c) {
                     // input row p feeds output q = p - M - dy, ring slot q mod P
@@ -203,6 +224,12 @@ __global__ __launch_bounds__(NW * 64) void k_rowrun(
 // their own sites in registers.  The initial projection and the final FP64
 // output-of-interest reduction are fused in.
 // ---------------------------------------------------------------------------
+// LDS row stride of the resident kernel: n plus the 2m halo, rounded up to
+// an even count so that paired window loads stay aligned.
+__host__ __device__ constexpr int resident_row_stride(int n, int M) {
+    return (n + 2 * M + 1) & ~1;
+}
+
 template <int R2, int R, int B, class TS, class TA, bool GAUSS>
 __global__ __launch_bounds__(512) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
@@ -216,7 +243,7 @@ __global__ __launch_bounds__(512) void k_resident(
     __shared__ double red[16];
 
     const int n = geo->n;
-    const int TW = n + 2 * M;
+    const int TW = resident_row_stride(n, M);
     const int sidx = ids[blockIdx.x];
     const SampleDesc d = sd[sidx];
     TS *g_state = state + d.offset;
@@ -246,20 +273,20 @@ __global__ __launch_bounds__(512) void k_resident(
         }
 
     for (int step = 0; step < nsteps; ++step) {
-        // Publish the state (and its periodic column halo) to LDS.
+        // Publish the state (and its periodic column halo) to LDS.  A column
+        // without a halo copy writes its value twice to the same place.
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            const int y = y0 + q;
-            if (y < n) {
-                TS *row = lds + y * TW + M;
+        for (int c = 0; c < R; ++c) {
+            const int x = xb + c;
+            if (x < n) {
+                const int xh = x < M ? x + n : (x >= n - M ? x - n : x);
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const int x = xb + c;
-                    if (x < n) {
+                for (int q = 0; q < B; ++q) {
+                    if (y0 + q < n) {
+                        TS *row = lds + (y0 + q) * TW + M;
                         const TS v = to_store<TS>(st[q][c]);
                         row[x] = v;
-                        if (x < M) row[x + n] = v;
-                        if (x >= n - M) row[x - n] = v;
+                        row[xh] = v;
                     }
                 }
             }
@@ -273,12 +300,14 @@ __global__ __launch_bounds__(512) void k_resident(
             for (int c = 0; c < R; ++c) acc[q][c] = TA(0);
 #pragma unroll
         for (int i = 0; i < ROWS; ++i) {
-            int r = rstart + i;  // scalar: wrap onto the torus
-            while (r >= n) r -= n;
+            // wrap onto the torus (rstart < n, i < B + 2M < n + 16 <= 2n)
+            int r = rstart + i;
+            r -= r >= n ? n : 0;
+            r -= r >= n ? n : 0;
             const TS *rp = lds + r * TW + xr;
             TA win[WIN];
-#pragma unroll
-            for (int j = 0; j < WIN; ++j) win[j] = to_acc<TA>(rp[j]);
+            // row stride and xr are even when R is even
+            load_window<WIN, (R % 2 == 0)>(rp, win);
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 // input row i feeds output q = i - M - dy

@@ -469,7 +469,7 @@ int check_algo_flags(int32_t algo) {
 
 extern "C" {
 
-int nlch_version(void) { return 1; }
+int nlch_version(void) { return 2; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 
@@ -673,12 +673,13 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models, const nlch_samp
     return NLCH_OK;
 }
 
-int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, const double *alpha,
-                  mfmc_result *out, void *hip_stream) {
+int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, int64_t y_stride,
+                  const double *alpha, mfmc_result *out, void *hip_stream) {
     if (K < 1 || K > NLCH_MFMC_MAX_K)
         return fail(NLCH_EINVAL, "K must be in [1, %d]", NLCH_MFMC_MAX_K);
     if (!m || !y_dev || !out) return fail(NLCH_EINVAL, "m, y_dev and out must be non-NULL");
     if (m[0] < 2) return fail(NLCH_EINVAL, "m[0] must be >= 2");
+    if (y_stride < 1) return fail(NLCH_EINVAL, "y_stride must be >= 1");
     for (int j = 1; j < K; ++j)
         if (m[j] < m[j - 1]) return fail(NLCH_EINVAL, "sample counts must be non-decreasing");
     for (int j = 0; j < K; ++j)
@@ -692,7 +693,7 @@ int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, const
     int rc = dev_ctx(&ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    HIP_TRY(launch_moments(K, y_dev, m, ctx->mom, s));
+    HIP_TRY(launch_moments(K, y_dev, m, y_stride, ctx->mom, s));
     HIP_TRY(hipMemcpyAsync(ctx->mom_h, ctx->mom, sizeof(double) * 8 * K, hipMemcpyDeviceToHost,
                            s));
     HIP_TRY(hipStreamSynchronize(s));

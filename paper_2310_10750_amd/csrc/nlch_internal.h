@@ -75,7 +75,7 @@ bool resident_supported(int prec, bool acc64, int R2, int kernel, int n);
 hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
                            int nsteps, double *ooi, hipStream_t s);
 hipError_t launch_moments(int K, const double *const *y, const int64_t *m,
-                          double *out, hipStream_t s);
+                          int64_t stride, double *out, hipStream_t s);
 
 // List of R2 values with compiled row-run kernels.
 int rowrun_r2_list(int64_t *out, int cap);

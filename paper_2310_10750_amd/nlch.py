@@ -96,7 +96,7 @@ def load():
                                      ctypes.POINTER(nlch_sample), i64, i32, i32,
                                      i32, vp, vp, vp, vp]
     lib.nlch_solve_batch.restype = ctypes.c_int
-    lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp),
+    lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64,
                                   pd, ctypes.POINTER(mfmc_result), vp]
     lib.mfmc_estimate.restype = ctypes.c_int
     lib.nlch_rowrun_supported.argtypes = [ctypes.POINTER(i64), i32]
@@ -193,8 +193,9 @@ def nlch_solve_batch(models, samples, nsteps: int, precision: int, algo: int, st
                                    _ptr(scratch), _ptr(ooi_out), _stream(stream)))
 
 
-def mfmc_estimate(ys, m, alpha=None, stream=None) -> dict:
-    """ys: K device arrays (float64) of model outputs; m: K sample counts."""
+def mfmc_estimate(ys, m, alpha=None, stream=None, y_stride=1) -> dict:
+    """ys: K device arrays (float64) of model outputs (or raw addresses), the
+    i-th output of model j at ys[j][i * y_stride]; m: K sample counts."""
     K = len(ys)
     mm = (ctypes.c_int64 * K)(*[int(v) for v in m])
     yp = (ctypes.c_void_p * K)(*[_ptr(y) for y in ys])
@@ -202,7 +203,8 @@ def mfmc_estimate(ys, m, alpha=None, stream=None) -> dict:
     if alpha is not None:
         al = (ctypes.c_double * max(1, K - 1))(*[float(a) for a in alpha])
     res = mfmc_result()
-    _check(load().mfmc_estimate(K, mm, yp, al, ctypes.byref(res), _stream(stream)))
+    _check(load().mfmc_estimate(K, mm, yp, int(y_stride), al, ctypes.byref(res),
+                                _stream(stream)))
     return {
         "q_mfmc": res.q_mfmc,
         "q_mc": res.q_mc,
