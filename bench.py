@@ -59,13 +59,12 @@ def kernel_source_hash():
 
 
 def algorithmic_ops(m: int, kernel: int) -> int:
-    """VALU lane-operations per site-step of the row-run evaluation:
-    2m window adds + (2m+1) accumulation adds + 6 for the update and clamp
-    (constant kernel); the Gaussian adds m + (2m+1) weight multiplies."""
-    ops = 2 * m + (2 * m + 1) + 6
-    if kernel == 1:
-        ops += m + (2 * m + 1)
-    return ops
+    """VALU lane-operations per site-step of the row-run evaluation: 2m for the
+    window sums (m pair adds, m accumulations -- fused multiply-adds for the
+    Gaussian kernel), 2m+1 for adding the window sums of the 2m+1 disc rows
+    (adds, or fused multiply-adds), and 6 for the update and the projection.
+    A fused multiply-add counts as one lane-operation."""
+    return 2 * m + (2 * m + 1) + 6
 
 
 def stored_traffic(kernel_name: str):
@@ -156,8 +155,15 @@ def main():
                                   scratch, ooi, stream)
             if i is not None:
                 ev_e[i].record(stream)
+        if level_counts[0] < 2:  # a single high-fidelity draw: no moments
+            stream.synchronize()
+            return None
         return nlch.mfmc_estimate(level_ptrs, level_counts, stream=stream, y_stride=2)
 
+    # A plain elementwise copy of known size (the state buffer), run once
+    # outside the timed region: its HBM counters calibrate the solver's.
+    with torch.cuda.stream(stream):
+        torch.add(init, 0, out=scratch)
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -198,8 +204,10 @@ def main():
                    "time_steps": w.nsteps, "precision": prec, "algo": args.algo},
         "roofline": roofline,
         "hbm_state_gbs": round(hbm_gbs, 1),
-        "mc_estimate": {"q_mc": est["q_mc"], "var": est["var"][0]},
     }
+    if est is not None:
+        out["mfmc_estimate"] = {"q_mfmc": est["q_mfmc"], "q_mc": est["q_mc"],
+                                "levels": level_counts, "alpha": est["alpha"]}
 
     # FP64, one sample per call, one launch per step, no graph.
     if not args.no_fp64_baseline:

@@ -16,6 +16,7 @@ namespace {
 
 constexpr int kElemThreads = 256;
 constexpr int kElemItems = 8;
+constexpr int64_t kOoiChunk = 16384;
 
 template <class TS>
 __global__ __launch_bounds__(kElemThreads) void k_project(
@@ -53,23 +54,40 @@ __global__ __launch_bounds__(kElemThreads) void k_count_nonfinite(
     if (bad) atomicAdd(counter, bad);
 }
 
+// Output of interest, pass 1: FP64 partial sums of fixed chunks of every
+// sample's state (one workgroup per chunk).
 template <class TS>
-__global__ __launch_bounds__(256) void k_ooi(const SampleDesc *__restrict__ sd,
-                                             const int32_t *__restrict__ ids,
-                                             int64_t nn, const TS *__restrict__ st,
-                                             double *__restrict__ ooi) {
+__global__ __launch_bounds__(256) void k_ooi_partial(const SampleDesc *__restrict__ sd,
+                                                     const int32_t *__restrict__ ids,
+                                                     int64_t nn, int chunks,
+                                                     const TS *__restrict__ st,
+                                                     double *__restrict__ partial) {
     __shared__ double red[4];
-    const int sidx = ids[blockIdx.x];
-    const SampleDesc d = sd[sidx];
+    const int b = blockIdx.x;
+    const SampleDesc d = sd[ids[b / chunks]];
+    const int64_t lo = (int64_t)(b % chunks) * kOoiChunk;
+    const int64_t hi = lo + kOoiChunk < nn ? lo + kOoiChunk : nn;
     const TS *s = st + d.offset;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < nn; i += 256) acc += (double)s[i];
-    double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) {
-        double mean = tot / (double)nn;
-        ooi[2 * (int64_t)sidx] = mean;
-        ooi[2 * (int64_t)sidx + 1] = 0.5 * (1.0 + mean);
-    }
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += (double)s[i];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[b] = tot;
+}
+
+// Pass 2: per sample, the chunk sums in chunk order -> mean and
+// f_1 = (1 + mean)/2 (eq. ooi).
+__global__ __launch_bounds__(64) void k_ooi_final(const int32_t *__restrict__ ids, int64_t nn,
+                                                  int chunks,
+                                                  const double *__restrict__ partial,
+                                                  double *__restrict__ ooi) {
+    const int j = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += partial[(int64_t)j * chunks + c];
+    const double mean = s / (double)nn;
+    const int64_t sidx = ids[j];
+    ooi[2 * sidx] = mean;
+    ooi[2 * sidx + 1] = 0.5 * (1.0 + mean);
 }
 
 constexpr int kDirTX = 64, kDirTY = 16, kDirThreads = 256;
@@ -179,24 +197,29 @@ hipError_t launch_count_nonfinite(int prec, const Group &g, const void *src,
     return hipGetLastError();
 }
 
-hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi,
-                      int, hipStream_t s) {
+int ooi_chunks(int n) { return (int)(((int64_t)n * n + kOoiChunk - 1) / kOoiChunk); }
+
+hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi, int,
+                      hipStream_t s) {
     const int64_t nn = (int64_t)g.n * g.n;
-    dim3 grid((unsigned)g.nids), block(256);
+    const int ch = ooi_chunks(g.n);
+    dim3 grid((unsigned)(ch * g.nids)), block(256);
     switch (prec) {
         case kF64:
-            hipLaunchKernelGGL((k_ooi<double>), grid, block, 0, s, g.sd, g.ids, nn,
-                               (const double *)state, ooi);
+            hipLaunchKernelGGL((k_ooi_partial<double>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const double *)state, g.partial);
             break;
         case kF32:
-            hipLaunchKernelGGL((k_ooi<float>), grid, block, 0, s, g.sd, g.ids, nn,
-                               (const float *)state, ooi);
+            hipLaunchKernelGGL((k_ooi_partial<float>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const float *)state, g.partial);
             break;
         default:
-            hipLaunchKernelGGL((k_ooi<half_t>), grid, block, 0, s, g.sd, g.ids, nn,
-                               (const half_t *)state, ooi);
+            hipLaunchKernelGGL((k_ooi_partial<half_t>), grid, block, 0, s, g.sd, g.ids, nn, ch,
+                               (const half_t *)state, g.partial);
             break;
     }
+    hipLaunchKernelGGL(k_ooi_final, dim3((unsigned)g.nids), dim3(64), 0, s, g.ids, nn, ch,
+                       g.partial, ooi);
     return hipGetLastError();
 }
 

@@ -13,40 +13,58 @@ namespace nlch {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-template <int R2>
-struct RowrunShape {
-    static constexpr int M = Disc<R2>::M;
-    static constexpr int R = (M >= 24) ? 1 : 2;
-    static constexpr int NW = (M >= 24) ? 2 : 4;
-    static constexpr int TX = 64 * R;
-    static constexpr int TW = TX + 2 * M;
-};
+// Streaming shape: lanes own R columns of a 64R-column strip.  R = 2 halves
+// the window reads per site; R = 1 is used for wide discs (large register
+// rings) and for small batches, where twice the strips give twice the waves.
+// A wave's band height B trades parallelism (enough waves to fill 256 CUs
+// about 12 deep) against the 2m-row window overhead of each band, and never
+// goes below max(16, 2m) rows.
+inline int stream_band_rows(int n, int M, int TX, int nids) {
+    const int strips = (n + TX - 1) / TX;
+    const int64_t target_waves = 3072;
+    const int64_t have = (int64_t)strips * nids;
+    int64_t bands = (target_waves + have - 1) / have;
+    if (bands < 1) bands = 1;
+    int B = (int)((n + bands - 1) / bands);
+    const int bmin = M * 2 > 16 ? M * 2 : 16;
+    if (B < bmin) B = bmin;
+    if (B > n) B = n;
+    return B;
+}
+
+inline int stream_lanes_cols(int n, int M, int nids) {
+    if (M >= 24) return 1;
+    // waves available with R = 2 at the minimum band height
+    const int bmin = M * 2 > 16 ? M * 2 : 16;
+    const int64_t waves2 = (int64_t)((n + 127) / 128) * ((n + bmin - 1) / bmin) * nids;
+    return waves2 < 2048 ? 1 : 2;
+}
+
+template <int R2, int R, class TS, class TA, bool GAUSS>
+hipError_t stream_launch(const Group &g, const void *in, void *out, hipStream_t s) {
+    constexpr int M = Disc<R2>::M;
+    constexpr int TX = 64 * R;
+    const int B = stream_band_rows(g.n, M, TX, g.nids);
+    const int strips = (g.n + TX - 1) / TX;
+    const int bands = (g.n + B - 1) / B;
+    const int64_t nb = (int64_t)strips * bands * g.nids;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
+                       g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, B, strips, bands,
+                       (int)nb);
+    return hipGetLastError();
+}
 
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t s) {
-    using S = RowrunShape<R2>;
-    constexpr int M = S::M;
-    int B = (M >= 24) ? 64 : 32;
-    while (B > 8 && (size_t)(S::NW * B + 2 * M) * S::TW * sizeof(TS) > kLdsBytes) B /= 2;
-    while (B > 8 && S::NW * (B / 2) >= g.n) B /= 2;  // small lattices: short tiles
-    const int TY = S::NW * B;
-    const size_t lds = (size_t)(TY + 2 * M) * S::TW * sizeof(TS);
-    if (lds > kLdsBytes) return hipErrorInvalidValue;
-    const int tiles_x = (g.n + S::TX - 1) / S::TX;
-    const int tiles_y = (g.n + TY - 1) / TY;
-    const int tps = tiles_x * tiles_y;
-    const int64_t nb = (int64_t)tps * g.nids;
-    if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    auto f = k_rowrun<R2, S::R, S::NW, TS, TA, GAUSS>;
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kLdsBytes);
-        attr = true;
+    constexpr int M = Disc<R2>::M;
+    if constexpr (M >= 24) {
+        return stream_launch<R2, 1, TS, TA, GAUSS>(g, in, out, s);
+    } else {
+        if (stream_lanes_cols(g.n, M, g.nids) == 1)
+            return stream_launch<R2, 1, TS, TA, GAUSS>(g, in, out, s);
+        return stream_launch<R2, 2, TS, TA, GAUSS>(g, in, out, s);
     }
-    hipLaunchKernelGGL(f, dim3((unsigned)nb), dim3(S::NW * 64), lds, s, g.sd, g.ids, g.geo,
-                       (const TS *)in, (TS *)out, B, tiles_x, tps, (int)nb);
-    return hipGetLastError();
 }
 
 // Resident layout: lanes own R adjacent columns, waves own bands of B rows.

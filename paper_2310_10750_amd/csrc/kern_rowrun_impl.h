@@ -121,49 +121,55 @@ __device__ __forceinline__ void row_windows(const TA *win, const TA *g, Add &&ad
 }
 
 // ---------------------------------------------------------------------------
-// Streaming step: one workgroup = NW waves stacked vertically over a tile of
-// 64R columns x NW*B rows of one sample.  The halo tile (rows and columns
-// widened by m, wrapped periodically) is staged in LDS once; each wave walks
-// its B output rows with a ring of 2m+1 accumulator rows and writes finished
-// sites straight to the output buffer.
+// Streaming step: a workgroup is one wave that owns a strip of 64R columns
+// and a band of B output rows of one sample.  It walks the B + 2m input rows
+// of its band once: each row segment (its 64R columns plus the m-column
+// periodic halo on either side) is fetched with coalesced loads one row
+// ahead, staged through a two-row LDS ring private to the wave, turned into
+// window sums and added into a register ring of 2m+1 pending output rows.
+// A finished row is updated and written straight to the output buffer.
+// Occupancy is bounded only by registers, not by shared tiles.
 // ---------------------------------------------------------------------------
-template <int R2, int R, int NW, class TS, class TA, bool GAUSS>
-__global__ __launch_bounds__(NW * 64) void k_rowrun(
+template <int R2, int R, class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(64) void k_stream(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const TS *__restrict__ in,
-    TS *__restrict__ out, int B, int tiles_x, int tiles_per_sample, int nblocks) {
+    TS *__restrict__ out, int B, int strips, int bands, int nblocks) {
     constexpr int M = Disc<R2>::M, P = Disc<R2>::P;
     constexpr int TX = 64 * R;
     constexpr int TW = TX + 2 * M;
     constexpr int WIN = 2 * M + R;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    TS *tile = reinterpret_cast<TS *>(smem_raw);
+    constexpr int CPL = (TW + 63) / 64;  // row-segment elements per lane
+    // the ring holds the arithmetic type: a narrow state is widened once per
+    // staged element instead of once per window read
+    __shared__ __align__(16) TA ring[2][TW];
 
     const int n = geo->n;
     const int bidx = xcd_remap(blockIdx.x, nblocks);
-    const SampleDesc d = sd[ids[bidx / tiles_per_sample]];
-    const int t = bidx % tiles_per_sample;
-    const int TY = NW * B;
-    const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * TY;
+    const int per_sample = strips * bands;
+    const SampleDesc d = sd[ids[bidx / per_sample]];
+    const int t = bidx % per_sample;
+    const int x0 = (t % strips) * TX;
+    const int y0 = (t / strips) * B;
     const TS *src = in + d.offset;
     TS *dst = out + d.offset;
-
-    // Stage rows y0-M .. y0+TY+M-1, columns x0-M .. x0+TX+M-1 (periodic).
-    const int rows_tile = TY + 2 * M;
-    for (int i = threadIdx.x; i < rows_tile * TW; i += NW * 64) {
-        const int r = i / TW, c = i - r * TW;
-        int gy = (y0 - M + r) % n;
-        gy += gy < 0 ? n : 0;
-        int gx = (x0 - M + c) % n;
-        gx += gx < 0 ? n : 0;
-        tile[i] = src[(int64_t)gy * n + gx];
-    }
-    __syncthreads();
-
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     const int c0 = lane * R;
-    const int rowbase = wave * B;
+    const int rows = (y0 + B <= n ? B : n - y0) + 2 * M;
+
+    int gxs[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        int gx = (x0 - M + lane + 64 * k) % n;
+        gxs[k] = gx + (gx < 0 ? n : 0);
+    }
+    int gy = (y0 - M) % n;
+    gy += gy < 0 ? n : 0;
+    TS pre[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k)
+        if (lane + 64 * k < TW) pre[k] = src[(int64_t)gy * n + gxs[k]];
+
     const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
 #pragma unroll
@@ -175,36 +181,51 @@ __global__ __launch_bounds__(NW * 64) void k_rowrun(
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[i][c] = TA(0);
 
-    const int rows = B + 2 * M;
     for (int pb = 0; pb < rows; pb += P) {
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int p = pb + i;
             if (p < rows) {
-                const TS *rp = tile + (rowbase + p) * TW + c0;
+                // stage row p, prefetch row p + 1
+                TA *slot = ring[i & 1 ? (pb & 1) ^ 1 : (pb & 1)];
+#pragma unroll
+                for (int k = 0; k < CPL; ++k)
+                    if (lane + 64 * k < TW) slot[lane + 64 * k] = to_acc<TA>(pre[k]);
+                gy = gy + 1 < n ? gy + 1 : 0;
+                if (p + 1 < rows) {
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k)
+                        if (lane + 64 * k < TW) pre[k] = src[(int64_t)gy * n + gxs[k]];
+                }
+                // centre values of the output finishing at this row
+                const int q = p - 2 * M;
+                const int y = y0 + q;
+                TS cen[R];
+                if (q >= 0) {
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        const int x = x0 + c0 + c;
+                        cen[c] = src[(int64_t)y * n + (x < n ? x : 0)];
+                    }
+                }
+                __syncthreads();  // one wave: makes the staged row visible
                 TA win[WIN];
-                // TW and c0 are even when R is even
-                load_window<WIN, (R % 2 == 0)>(rp, win);
+                load_window<WIN, (R % 2 == 0)>(slot + c0, win);
 #pragma unroll
                 for (int c = 0; c < R; ++c) {
-                    // input row p feeds output q = p - M - dy, ring slot q mod P
+                    // input row p feeds output q' = p - M - dy, ring slot q' mod P
                     row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
                         acc[((i - M - dy) % P + P) % P][c] += v;
                     });
                 }
-                // Output q = p - 2M is complete (ring slot (i+1) mod P).
                 const int done = (i + 1) % P;
-                const int q = p - 2 * M;
                 if (q >= 0) {
-                    const int ly = rowbase + q;
-                    const int y = y0 + ly;
-                    const TS *cen = tile + (ly + M) * TW + c0 + M;
 #pragma unroll
                     for (int c = 0; c < R; ++c) {
                         const int x = x0 + c0 + c;
                         const TA u = to_acc<TA>(cen[c]);
                         const TA lsum = ce * u - acc[done][c];
-                        if (y < n && x < n)
+                        if (x < n)
                             dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
                     }
                 }

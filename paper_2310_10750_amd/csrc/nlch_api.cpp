@@ -216,7 +216,7 @@ struct DevBuf {
 struct Batch {
     std::vector<uint8_t> key;
     int device = -1;
-    DevBuf geo, ewf, ewd, sd, ids;
+    DevBuf geo, ewf, ewd, sd, ids, partial;
     std::vector<Group> groups;           // launch groups
     std::vector<int> variant;            // per group
     std::map<std::vector<uint8_t>, hipGraphExec_t> graphs;
@@ -404,8 +404,18 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     HIP_TRY(hipMemcpy(b->sd.p, sd.data(), sizeof(SampleDesc) * sd.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&b->ids.p, sizeof(int32_t) * ids.size()));
     HIP_TRY(hipMemcpy(b->ids.p, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice));
+    // Chunk sums of the output-of-interest reduction (streaming groups).
+    std::vector<size_t> part_off(b->groups.size(), 0);
+    size_t npart = 1;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        part_off[gi] = npart;
+        if (b->variant[gi] != kResident)
+            npart += (size_t)ooi_chunks(b->groups[gi].n) * b->groups[gi].nids;
+    }
+    HIP_TRY(hipMalloc(&b->partial.p, sizeof(double) * npart));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         Group &g = b->groups[gi];
+        g.partial = reinterpret_cast<double *>(b->partial.p) + part_off[gi];
         g.geo = reinterpret_cast<const ModelGeo *>(b->geo.p) + g.model;
         g.ewf = reinterpret_cast<const float *>(b->ewf.p);
         g.ewd = reinterpret_cast<const double *>(b->ewd.p);

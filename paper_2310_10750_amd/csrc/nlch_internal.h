@@ -49,6 +49,7 @@ struct Group {
     const double *ewd;      //   (FP32 and FP64 copies, indexed from e_off)
     const SampleDesc *sd;   // device pointer to all sample descriptors
     const int32_t *ids;     // device pointer to this group's sample indices
+    double *partial;        // device scratch: ooi_chunks(n) doubles per sample
     int32_t nids;
     int32_t n, m, R2;
     int32_t kernel;
@@ -64,6 +65,7 @@ hipError_t launch_project(int prec, const Group &g, const void *src, void *dst,
                           hipStream_t s);
 hipError_t launch_count_nonfinite(int prec, const Group &g, const void *src,
                                   unsigned int *counter, hipStream_t s);
+int ooi_chunks(int n);
 hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi,
                       int per_sample_slots, hipStream_t s);
 hipError_t launch_direct_step(int prec, bool acc64, const Group &g,

@@ -75,3 +75,28 @@ def oracle_samples(orc, w, idx, prec, nsteps=None):
         for k, i in enumerate(ids):
             out[i] = (U[k], mean[k], f1[k])
     return out
+
+
+def one_step_sites(orc, w, batch, i, nsites=1500, seed=0):
+    """Max |GPU step - oracle step| over random sites of sample i, both
+    stepping from the GPU's current state of that sample (taken as stored).
+    Advances the sample by one step on the GPU."""
+    from paper_2310_10750_amd import nlch
+    s = w.samples[i]
+    m = w.models[s.model]
+    u = batch.sample_state(i)
+    rng = np.random.default_rng(seed)
+    sites = rng.choice(m.n * m.n, size=min(nsites, m.n * m.n), replace=False)
+    ref = orc.step_sites(u, sites, m.n, m.delta, m.kernel, s.amp, m.sigma, s.c_F,
+                         m.beta1, m.tau)
+    one = nlch.nlch_sample(s.model, 0, s.c_F, s.amp, 0)
+    off = batch.samples[i].offset
+    x = batch.state[off:off + m.n * m.n]
+    scr = batch.scratch[off:off + m.n * m.n]
+    import torch
+    o = torch.zeros(2, dtype=torch.float64, device=batch.state.device)
+    nlch.nlch_solve_batch(batch.models, [one], 1, nlch.PRECISIONS[batch.prec],
+                          nlch.NLCH_ALGO_AUTO, x, scr, o)
+    torch.cuda.synchronize()
+    got = batch.sample_state(i).reshape(-1)[sites]
+    return float(np.max(np.abs(got - ref)))

@@ -1,0 +1,141 @@
+"""Parity at the full sizes of the five workload recipes, in the launch
+configuration the benchmark uses (AUTO algorithm, graph replay).
+
+Where a full FP64 trajectory is affordable on the host it is compared whole on
+a subset of samples (OoI relative error and max |u| error); where it is not,
+the GPU state at several steps is checked site by site against one oracle
+step from that same state, and the invariants (|u| <= 1, finite OoI) are
+checked on every sample.
+"""
+import numpy as np
+import pytest
+
+from paper_2310_10750_amd import nlch, synth
+from tests.gpu_harness import DeviceBatch, one_step_sites, oracle_samples
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 1e-3}
+
+
+def _check_all(b):
+    o = b.ooi_host()
+    assert np.all(np.isfinite(o))
+    assert np.all((o[:, 1] >= 0) & (o[:, 1] <= 1))
+    assert float(torch.max(torch.abs(b.state.float()))) <= 1.0
+
+
+def test_c3_full_batch_sampled_oracle(orc):
+    """4096 x 128^2, delta = 8h, 500 steps, FP32 (the benchmark workload)."""
+    print("C3 full", flush=True)
+    w = synth.workload("C3")
+    b = DeviceBatch(w)
+    b.solve()
+    torch.cuda.synchronize()
+    _check_all(b)
+    idx = [0, 1, 2, 3, 1000, 2047, 3071, 4095]
+    ref = oracle_samples(orc, w, idx, "f32")
+    o = b.ooi_host()
+    for i in idx:
+        assert abs(o[i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2]), i
+    for i in (0, 4095):
+        assert one_step_sites(orc, w, b, i) <= STEP_TOL["f32"]
+
+
+def test_c3_fp16_storage_reported(orc):
+    """FP16 storage on the spinodal C3 trajectory: invariants hold; the OoI
+    error against FP64 is reported (rounding is amplified by the instability,
+    so it is not gated here)."""
+    w = synth.workload("C3", n_samples=64)
+    b = DeviceBatch(w, "f16")
+    b.solve()
+    torch.cuda.synchronize()
+    _check_all(b)
+    ref = oracle_samples(orc, w, [0, 1, 2, 3], "f16")
+    o = b.ooi_host()
+    errs = [abs(o[i, 1] - ref[i][2]) / abs(ref[i][2]) for i in range(4)]
+    print("C3 FP16 storage OoI rel err:", ["%.2e" % e for e in errs])
+    assert max(errs) < 0.05
+
+
+def test_c2_single_high_fidelity_sample(orc):
+    """512^2, delta = 16h (797-point disc), four-nuclei data, FP32."""
+    print("C2 full", flush=True)
+    w = synth.workload("C2")
+    b = DeviceBatch(w)
+    # full-length run, then per-site one-step checks along the trajectory
+    b.solve(nsteps=w.nsteps)
+    torch.cuda.synchronize()
+    _check_all(b)
+    assert one_step_sites(orc, w, b, 0, seed=1) <= STEP_TOL["f32"]
+    b.reset()
+    b.solve(nsteps=500)
+    assert one_step_sites(orc, w, b, 0, seed=2) <= STEP_TOL["f32"]
+    # whole trajectory on the first 100 steps against the oracle
+    b.reset()
+    b.solve(nsteps=100)
+    torch.cuda.synchronize()
+    ref = oracle_samples(orc, w, [0], "f32", nsteps=100)[0]
+    assert abs(b.ooi_host()[0, 1] - ref[2]) <= 1e-6 * abs(ref[2])
+    assert np.max(np.abs(b.sample_state(0) - ref[0])) <= 1e-4
+
+
+def test_c4_mfmc_ensemble(orc):
+    """1024^2 x8, 256^2 x64, 128^2 x512, 64^2 x4096, Gaussian kernel, delta =
+    1/32, 100 steps, one call; FP64 MFMC estimate of the ensemble."""
+    print("C4 full", flush=True)
+    from oracle import mfmc
+    w = synth.workload("C4")
+    b = DeviceBatch(w)
+    b.solve()
+    torch.cuda.synchronize()
+    _check_all(b)
+    o = b.ooi_host()
+    counts = w.level_counts
+    starts = np.cumsum([0] + counts[:-1])
+    # whole trajectories: a few samples of each coarse level
+    idx = [int(starts[1]), int(starts[1]) + 1, int(starts[2]), int(starts[2]) + 7,
+           int(starts[3]), int(starts[3]) + 100, int(starts[3]) + 4095]
+    ref = oracle_samples(orc, w, idx, "f32")
+    for i in idx:
+        assert abs(o[i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2]), i
+    # high-fidelity level: per-site one-step checks from the final state
+    for i in (0, 7):
+        assert one_step_sites(orc, w, b, i, seed=i) <= STEP_TOL["f32"]
+    # the estimator on the GPU outputs equals the FP64 reference
+    b.reset()
+    b.solve()
+    torch.cuda.synchronize()
+    o = b.ooi_host()
+    ptrs = [b.ooi.data_ptr() + 8 * (2 * int(s0) + 1) for s0 in starts]
+    got = nlch.mfmc_estimate(ptrs, counts, y_stride=2)
+    ys = [o[int(s0):int(s0) + c, 1] for s0, c in zip(starts, counts)]
+    exp = mfmc.mfmc_estimate(ys, counts)
+    assert abs(got["q_mfmc"] - exp["q_mfmc"]) <= 1e-13
+    np.testing.assert_allclose(got["alpha"], exp["alpha"], rtol=1e-10)
+    assert 0.0 < got["q_mfmc"] < 1.0
+
+
+def test_c5_large_horizon_fp16(orc):
+    """64 x 2048^2, delta = 32h (3209-point disc), FP16 storage, 100 steps:
+    per-site checks on the full batch; the FP16 OoI gate (1e-3) on a whole
+    trajectory of the same disc on a 256^2 lattice."""
+    print("C5 full", flush=True)
+    w = synth.workload("C5")
+    b = DeviceBatch(w)
+    b.solve()
+    torch.cuda.synchronize()
+    _check_all(b)
+    for i in (0, 63):
+        assert one_step_sites(orc, w, b, i, seed=i) <= STEP_TOL["f16"]
+    ws = synth.workload("C5", n=256, n_samples=2)
+    bs = DeviceBatch(ws)
+    bs.solve()
+    torch.cuda.synchronize()
+    ref = oracle_samples(orc, ws, [0, 1], "f16")
+    o = bs.ooi_host()
+    for i in (0, 1):
+        err = abs(o[i, 1] - ref[i][2]) / abs(ref[i][2])
+        print("C5-disc 256^2 FP16 OoI rel err %.2e" % err)
+        assert err <= 1e-3
