@@ -67,23 +67,17 @@ hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t 
     }
 }
 
-// Resident layout: lanes own R adjacent columns, waves own bands of B rows.
-inline void resident_shape(int n, int *R, int *B) {
-    *R = n <= 64 ? 1 : 2;
-    *B = 16;
-}
+// Resident layout: one wave per band of kResB rows, lanes own one (n = 64)
+// or two (n = 128) adjacent columns; built for these two lattice sizes.
+constexpr int kResB = 16;
 
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
                            hipStream_t s) {
     constexpr int M = Disc<R2>::M;
-    int R, B;
-    resident_shape(g.n, &R, &B);
-    const int tpb = ((g.n + R - 1) / R + 63) / 64 * 64;
-    const int nbands = (g.n + B - 1) / B;
-    const int threads = tpb * nbands;
-    const size_t lds = (size_t)g.n * resident_row_stride(g.n, M) * sizeof(TS);
-    if (threads > 512 || lds > kLdsBytes - 1024) return hipErrorInvalidValue;
+    const int threads = 64 * (g.n / kResB);
+    const size_t lds = resident_lds_bytes(g.n, M, kResB, sizeof(TS), sizeof(TA));
+    if ((g.n != 64 && g.n != 128) || lds > kLdsBytes - 1024) return hipErrorInvalidValue;
     auto go = [&](auto f) {
         static bool attr = false;
         if (!attr) {
@@ -92,12 +86,12 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
             attr = true;
         }
         hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(threads), lds, s, g.sd, g.ids,
-                           g.geo, (TS *)state, nsteps, ooi, tpb);
+                           g.geo, (TS *)state, nsteps, ooi);
     };
-    if (R == 1)
-        go(k_resident<R2, 1, 16, TS, TA, GAUSS>);
+    if (g.n == 64)
+        go(k_resident<R2, 64, kResB, TS, TA, GAUSS>);
     else
-        go(k_resident<R2, 2, 16, TS, TA, GAUSS>);
+        go(k_resident<R2, 128, kResB, TS, TA, GAUSS>);
     return hipGetLastError();
 }
 
@@ -117,10 +111,10 @@ bool resident_has_typed(int R2, int n) {
     if (R2 == v) in_list = true;
     NLCH_RESIDENT_R2_LIST(NLCH_X)
 #undef NLCH_X
-    // 16 <= n keeps the band walk within two periods of the torus
-    if (!in_list || n > 128 || n < 16) return false;
+    // built for n = 64 and n = 128 (whole bands, one wave per band)
+    if (!in_list || (n != 64 && n != 128)) return false;
     const int M = cisqrt(R2);
-    return (size_t)n * resident_row_stride(n, M) * sizeof(TS) <= kLdsBytes - 1024;
+    return M <= kResB && resident_lds_bytes(n, M, kResB, sizeof(TS), sizeof(TA)) <= kLdsBytes - 1024;
 }
 
 template <class TS, class TA>

@@ -99,6 +99,9 @@ __device__ __forceinline__ void sfor(F &&f) {
 
 constexpr int cabs(int v) { return v < 0 ? -v : v; }
 
+// Accumulators start at -0.0, the exact identity of IEEE addition (x + -0 is
+// x for every x, +0 included), so the first add of each sum folds away.
+
 // Window sums of one input row for column c (window values win[c .. c+2M])
 // grown incrementally, each added into the outputs that use its half-width:
 // add(dy, value) receives g(|dy|) * H_{w(dy)} (or H for the constant kernel).
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(64) void k_stream(
 #pragma unroll
     for (int i = 0; i < P; ++i)
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[i][c] = TA(0);
+        for (int c = 0; c < R; ++c) acc[i][c] = TA(-0.0);
 
     for (int pb = 0; pb < rows; pb += P) {
 #pragma unroll
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(64) void k_stream(
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[done][c] = TA(0);
+                for (int c = 0; c < R; ++c) acc[done][c] = TA(-0.0);
             }
         }
     }
@@ -239,42 +242,63 @@ __global__ __launch_bounds__(64) void k_stream(
 // ---------------------------------------------------------------------------
 // LDS-resident multi-step kernel: one workgroup holds one whole n x n sample
 // in LDS (rows padded with an m-column periodic halo) and runs every step
-// without touching HBM.  Threads own R columns x B rows of the state in
-// registers; per step they publish the state to LDS, then walk their band
-// (B + 2m input rows, fully unrolled, static accumulator indices) and update
-// their own sites in registers.  The initial projection and the final FP64
-// output-of-interest reduction are fused in.
+// without touching HBM.  Wave b owns the band of B rows starting at b*B
+// (n is a multiple of B) and R columns per lane; it keeps its sites in
+// registers.  Per step it publishes them to LDS, then walks only its own B
+// input rows: window sums of a row feed the 2m+1 output rows around it,
+// including the m rows above and below the band, whose partial sums go to
+// the neighbouring bands through an LDS exchange area.  After a barrier
+// each band adds the partial sums it received and updates its sites.  Every
+// input row is read and turned into window sums exactly once per step.
+// The initial projection and the final FP64 output-of-interest reduction
+// are fused in.
 // ---------------------------------------------------------------------------
+
 // LDS row stride of the resident kernel: n plus the 2m halo, rounded up to
 // an even count so that paired window loads stay aligned.
 __host__ __device__ constexpr int resident_row_stride(int n, int M) {
     return (n + 2 * M + 1) & ~1;
 }
 
-template <int R2, int R, int B, class TS, class TA, bool GAUSS>
+// LDS bytes of the resident kernel: the state rows, then for every band an
+// "up" and a "down" exchange block of m rows of n partial sums.
+__host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, size_t ts,
+                                                        size_t ta) {
+    return (size_t)n * resident_row_stride(n, M) * ts + 2 * (size_t)(n / B) * M * n * ta;
+}
+
+template <int R2, int N, int B, class TS, class TA, bool GAUSS>
 __global__ __launch_bounds__(512) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
-    double *__restrict__ ooi, int tpb) {
+    double *__restrict__ ooi) {
+    // The lattice size is a compile-time constant so that every LDS offset
+    // below is an instruction immediate rather than a register.
     constexpr int M = Disc<R2>::M;
+    constexpr int R = N <= 64 ? 1 : 2;  // columns per lane, n <= 64 R
     constexpr int WIN = 2 * M + R;
-    constexpr int ROWS = B + 2 * M;
+    constexpr int Q = B + 2 * M;  // outputs fed by one band: its rows +- m
+    static_assert(M <= B, "partial sums must only reach the adjacent bands");
+    static_assert(N % B == 0 && N <= 64 * R, "one wave per band");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    TS *lds = reinterpret_cast<TS *>(smem_raw);
     __shared__ double red[16];
 
-    const int n = geo->n;
-    const int TW = resident_row_stride(n, M);
+    constexpr int n = N;
+    constexpr int TW = resident_row_stride(N, M);
+    constexpr int NB = N / B;
+    TS *lds = reinterpret_cast<TS *>(smem_raw);
+    TA *xup = reinterpret_cast<TA *>(smem_raw + (size_t)n * TW * sizeof(TS));
+    TA *xdn = xup + (size_t)NB * M * n;
     const int sidx = ids[blockIdx.x];
     const SampleDesc d = sd[sidx];
     TS *g_state = state + d.offset;
-    // band is uniform per wave (tpb % 64 == 0): keep its arithmetic scalar
-    const int band = __builtin_amdgcn_readfirstlane(threadIdx.x / tpb);
-    const int xb = (threadIdx.x - band * tpb) * R;
+    // one wave per band (n <= 64 R); band arithmetic stays scalar
+    const int band = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xb = (threadIdx.x & 63) * R;
     const int y0 = band * B;
-    int rstart = (y0 - M) % n;  // first input row of the band walk
-    rstart += rstart < 0 ? n : 0;
     const int xr = xb + R <= n ? xb : n - R;  // in-row read position for idle lanes
+    const int bup = band + 1 < NB ? band + 1 : 0;
+    const int bdn = band > 0 ? band - 1 : NB - 1;
 
     const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
@@ -287,9 +311,9 @@ __global__ __launch_bounds__(512) void k_resident(
     for (int q = 0; q < B; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const int y = y0 + q, x = xb + c;
+            const int x = xb + c;
             TA v = TA(0);
-            if (y < n && x < n) v = to_acc<TA>(g_state[(int64_t)y * n + x]);
+            if (x < n) v = to_acc<TA>(g_state[(int64_t)(y0 + q) * n + x]);
             st[q][c] = clamp1(v);
         }
 
@@ -303,52 +327,67 @@ __global__ __launch_bounds__(512) void k_resident(
                 const int xh = x < M ? x + n : (x >= n - M ? x - n : x);
 #pragma unroll
                 for (int q = 0; q < B; ++q) {
-                    if (y0 + q < n) {
-                        TS *row = lds + (y0 + q) * TW + M;
-                        const TS v = to_store<TS>(st[q][c]);
-                        row[x] = v;
-                        row[xh] = v;
-                    }
+                    TS *row = lds + (y0 + q) * TW + M;
+                    const TS v = to_store<TS>(st[q][c]);
+                    row[x] = v;
+                    row[xh] = v;
                 }
             }
         }
         __syncthreads();
 
-        TA acc[B][R];
+        // acc[M + q] collects output row y0 + q, q in [-m, B + m).
+        TA acc[Q][R];
 #pragma unroll
-        for (int q = 0; q < B; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int c = 0; c < R; ++c) acc[q][c] = TA(0);
+            for (int c = 0; c < R; ++c) acc[q][c] = TA(-0.0);
+        const TS *rp0 = lds + y0 * TW + xr;
 #pragma unroll
-        for (int i = 0; i < ROWS; ++i) {
-            // wrap onto the torus (rstart < n, i < B + 2M < n + 16 <= 2n)
-            int r = rstart + i;
-            r -= r >= n ? n : 0;
-            r -= r >= n ? n : 0;
-            const TS *rp = lds + r * TW + xr;
+        for (int i = 0; i < B; ++i) {
+            // rows are independent: keep the compiler from hoisting every
+            // row's loads (and their registers) to the top of the walk
+            asm volatile("" ::: "memory");
             TA win[WIN];
-            // row stride and xr are even when R is even
-            load_window<WIN, (R % 2 == 0)>(rp, win);
+            load_window<WIN, (R % 2 == 0)>(rp0 + i * TW, win);
 #pragma unroll
             for (int c = 0; c < R; ++c) {
-                // input row i feeds output q = i - M - dy
+                // input row i feeds output q = i - dy
                 row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
-                    const int q = i - M - dy;
-                    if (q >= 0 && q < B) acc[q][c] += v;
+                    acc[M + i - dy][c] += v;
                 });
             }
-            // Output row q = i - 2M is complete: update in registers.
-            const int q = i - 2 * M;
-            if (q >= 0 && q < B) {
+        }
+        // Hand the overhanging partial sums to the adjacent bands.
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const TA u = st[q][c];
-                    const TA lsum = ce * u - acc[q][c];
-                    st[q][c] = to_acc<TA>(to_store<TS>(update<TA>(u, lsum, a, bcoef)));
+        for (int c = 0; c < R; ++c) {
+            const int x = xb + c;
+            if (x < n) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    xup[((size_t)band * M + j) * n + x] = acc[j][c];
+                    xdn[((size_t)band * M + j) * n + x] = acc[B + M + j][c];
                 }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int x = xr + c;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                acc[M + j][c] += xdn[((size_t)bdn * M + j) * n + x];
+                acc[B + j][c] += xup[((size_t)bup * M + j) * n + x];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const TA u = st[q][c];
+                const TA lsum = ce * u - acc[M + q][c];
+                st[q][c] = to_acc<TA>(to_store<TS>(update<TA>(u, lsum, a, bcoef)));
+            }
     }
 
     // Write back and reduce the output of interest in FP64.
@@ -357,9 +396,9 @@ __global__ __launch_bounds__(512) void k_resident(
     for (int q = 0; q < B; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const int y = y0 + q, x = xb + c;
-            if (y < n && x < n) {
-                g_state[(int64_t)y * n + x] = to_store<TS>(st[q][c]);
+            const int x = xb + c;
+            if (x < n) {
+                g_state[(int64_t)(y0 + q) * n + x] = to_store<TS>(st[q][c]);
                 part += (double)st[q][c];
             }
         }

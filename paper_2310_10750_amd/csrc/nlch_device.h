@@ -26,6 +26,12 @@ template <class T>
 __device__ __forceinline__ T clamp1(T v) {
     return v < T(-1) ? T(-1) : (v > T(1) ? T(1) : v);
 }
+// FP32: IEEE 754-2019 maximum/minimum propagate NaN and map to one
+// v_maximum3_f32 and one v_minimum3_f32 on gfx950.
+template <>
+__device__ __forceinline__ float clamp1<float>(float v) {
+    return __builtin_elementwise_minimum(__builtin_elementwise_maximum(v, -1.0f), 1.0f);
+}
 
 // Update coefficients in the arithmetic type.
 template <class TA>
