@@ -7,8 +7,7 @@ this package, and this package imports nothing from the product.
 
 ``nlch_oracle.c`` holds the lattice solver (plain C, FP64, direct disc sums in
 canonical order); this module only marshals numpy arrays into it.  The MFMC
-estimator formulas live in :mod:`oracle.mfmc`, the dense brute-force operator in
-:mod:`oracle.brute`.
+estimator formulas live in :mod:`oracle.mfmc`.
 """
 from __future__ import annotations
 
