@@ -172,6 +172,41 @@ int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev,
                   int64_t y_stride, const double *alpha, mfmc_result *out,
                   void *hip_stream);
 
+/* Model selection (Sec. 3.1): a pool of K models (K <= NLCH_MFMC_MAX_POOL),
+ * model 0 the high-fidelity one, with per-sample costs cost[k] > 0 and
+ * correlations rho[k] = rho_{1,k} (rho[0] = 1, |rho[k]| <= 1).  Every subset
+ * holding model 0 and at least one surrogate (2^(K-1) - 1 candidates) is
+ * ordered by decreasing rho^2 and kept if the squared correlations strictly
+ * decrease (eq. conditiona) and eq. conditionb holds for j = 2..|S| with
+ * rho_{i_{|S|+1}} = 0.  Kept subsets are written to out (up to cap of them),
+ * sorted by increasing variance reduction ratio V (eq.
+ * variance_reduction_ratio; ties keep candidate order), each with
+ * B_min / C_1 = sqrt(V / (1 - rho_{1,i_2}^2)) (eq. bmin).  Returns the number
+ * of kept subsets (>= 0) or an NLCH_E* code; *n_candidates (if not NULL)
+ * receives 2^(K-1) - 1.  Host only. */
+#define NLCH_MFMC_MAX_POOL 16
+typedef struct mfmc_subset {
+    int32_t size;                        /* |S|                                 */
+    int32_t models[NLCH_MFMC_MAX_POOL];  /* pool indices, decreasing rho^2      */
+    double V;                            /* variance reduction ratio            */
+    double bmin_over_c1;                 /* minimum budget / C_1                */
+} mfmc_subset;
+int mfmc_select(int32_t K, const double *cost, const double *rho, mfmc_subset *out,
+                int32_t cap, int32_t *n_candidates);
+
+/* Sample allocation for budget B (Sec. 3.2): for a subset of S pool indices
+ * (model 0 first, decreasing rho^2), oversampling ratios r_j (eq. rk),
+ * m_1* = B / sum_j C_{i_j} r_j and m_j = m_1* r_j (eq. samples), written to
+ * m_real; m_int gets their floors (the Remark after eq. bmin).  When m_1* < 1
+ * (B below B_min) the samples follow the below-minimum-budget rule of Sec. 4:
+ * while some model j < S has m_j < j, the smallest such j and the models
+ * before it take m_l = l and the remaining budget B - sum_{l<=j} l C_{i_l} is
+ * shared by the later models with ratios relative to model j+1; budgets with
+ * B < sum_l l C_{i_l} are rejected (NLCH_EINVAL).  *m1_star (if not NULL)
+ * receives m_1* of eq. samples.  Host only. */
+int mfmc_allocate(int32_t S, const int32_t *subset, const double *cost, const double *rho,
+                  double budget, double *m_real, int64_t *m_int, double *m1_star);
+
 /* The disc sizes R2 for which ROWRUN kernels are compiled (RESIDENT uses the
  * subset with m <= 8): writes up to cap values into r2_list and returns the
  * total count. */

@@ -92,6 +92,8 @@ static int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+int nlch::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
 #define HIP_TRY(expr)                                                             \
     do {                                                                          \
         hipError_t e_ = (expr);                                                   \

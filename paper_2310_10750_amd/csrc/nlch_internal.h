@@ -79,6 +79,10 @@ hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
 hipError_t launch_moments(int K, const double *const *y, const int64_t *m,
                           int64_t stride, double *out, hipStream_t s);
 
+// Records the calling thread's error message (see nlch_last_error) and
+// returns code.
+int set_error(int code, const char *msg);
+
 // List of R2 values with compiled row-run kernels.
 int rowrun_r2_list(int64_t *out, int cap);
 

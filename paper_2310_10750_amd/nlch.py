@@ -36,6 +36,7 @@ NLCH_ALGO_NOGRAPH = 0x200
 NLCH_ALGO_CHECK_FINITE = 0x400
 
 NLCH_MFMC_MAX_K = 8
+NLCH_MFMC_MAX_POOL = 16
 
 PRECISIONS = {"f64": NLCH_F64, "f32": NLCH_F32, "f16": NLCH_F16_STORE}
 
@@ -61,6 +62,11 @@ class mfmc_result(ctypes.Structure):
     _fields_ = [("q_mfmc", ctypes.c_double), ("q_mc", ctypes.c_double),
                 ("mean_mj", _K8), ("mean_mjm1", _K8), ("var", _K8),
                 ("rho", _K8), ("alpha", _K8)]
+
+
+class mfmc_subset(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("models", ctypes.c_int32 * NLCH_MFMC_MAX_POOL),
+                ("V", ctypes.c_double), ("bmin_over_c1", ctypes.c_double)]
 
 
 class NlchError(RuntimeError):
@@ -99,6 +105,12 @@ def load():
     lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64,
                                   pd, ctypes.POINTER(mfmc_result), vp]
     lib.mfmc_estimate.restype = ctypes.c_int
+    lib.mfmc_select.argtypes = [i32, pd, pd, ctypes.POINTER(mfmc_subset), i32,
+                                ctypes.POINTER(i32)]
+    lib.mfmc_select.restype = ctypes.c_int
+    lib.mfmc_allocate.argtypes = [i32, ctypes.POINTER(i32), pd, pd, ctypes.c_double, pd,
+                                  ctypes.POINTER(i64), pd]
+    lib.mfmc_allocate.restype = ctypes.c_int
     lib.nlch_rowrun_supported.argtypes = [ctypes.POINTER(i64), i32]
     lib.nlch_rowrun_supported.restype = ctypes.c_int
     lib.nlch_last_error.argtypes = []
@@ -214,6 +226,36 @@ def mfmc_estimate(ys, m, alpha=None, stream=None, y_stride=1) -> dict:
         "rho": list(res.rho[:K]),
         "alpha": list(res.alpha[:K]),
     }
+
+
+def mfmc_select(cost, rho, cap=None):
+    """Feasible model subsets sorted by V: list of (models tuple, V, Bmin/C1),
+    and the number of candidates."""
+    K = len(cost)
+    c = (ctypes.c_double * K)(*[float(v) for v in cost])
+    r = (ctypes.c_double * K)(*[float(v) for v in rho])
+    cap = (1 << (K - 1)) if cap is None else cap
+    out = (mfmc_subset * max(1, cap))()
+    ncand = ctypes.c_int32()
+    n = load().mfmc_select(K, c, r, out, cap, ctypes.byref(ncand))
+    if n < 0:
+        _check(n)
+    res = [(tuple(out[i].models[:out[i].size]), out[i].V, out[i].bmin_over_c1)
+           for i in range(min(n, cap))]
+    return res, ncand.value
+
+
+def mfmc_allocate(subset, cost, rho, budget):
+    """(m_real list, m_int list, m1_star) for a subset of pool indices."""
+    S = len(subset)
+    sub = (ctypes.c_int32 * S)(*[int(v) for v in subset])
+    c = (ctypes.c_double * len(cost))(*[float(v) for v in cost])
+    r = (ctypes.c_double * len(rho))(*[float(v) for v in rho])
+    mr = (ctypes.c_double * S)()
+    mi = (ctypes.c_int64 * S)()
+    m1 = ctypes.c_double()
+    _check(load().mfmc_allocate(S, sub, c, r, float(budget), mr, mi, ctypes.byref(m1)))
+    return list(mr), list(mi), m1.value
 
 
 # ----------------------------------------------------------- marshalling --
