@@ -90,7 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--algo", type=int, default=0)
+    ap.add_argument("--algo", type=int, default=0x800,
+                    help="nlch algorithm word (default AUTO | AUTOTUNE)")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--fp64-samples", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -180,7 +181,7 @@ def main():
     # Dominant kernel: with every sample LDS-resident the solve is one launch.
     m0 = w.models[0]
     R2, mdisc, N, _ = nlch.nlch_disc(m0.n, m0.delta)
-    resident = all(mm.n <= 128 for mm in w.models) and args.algo in (0, 3)
+    resident = all(mm.n in (64, 128) for mm in w.models) and (args.algo & 0xff) in (0, 3)
     kname = "k_resident" if resident else "k_rowrun"
     ops = sum(algorithmic_ops(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
                               w.models[s.model].kernel) * w.models[s.model].n ** 2

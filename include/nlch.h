@@ -73,6 +73,12 @@ extern "C" {
 #define NLCH_ALGO_NOGRAPH 0x200  /* enqueue launches directly, no graph replay   */
 #define NLCH_ALGO_CHECK_FINITE 0x400 /* reject non-finite u0 with NLCH_EINVAL;
                                         synchronises hip_stream                 */
+#define NLCH_ALGO_AUTOTUNE 0x800 /* on the first call of a batch, time the
+                                    streaming kernel's launch shapes (lanes'
+                                    columns, band height) on the caller's
+                                    buffers (reads state, writes scratch),
+                                    keep the fastest; synchronises hip_stream.
+                                    Results do not depend on the shape.       */
 
 /* One fidelity level ("model"): lattice, horizon, kernel and evolution
  * parameters (Sec. 2.1 and Sec. 4). */

@@ -13,42 +13,20 @@ namespace nlch {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// Streaming shape: lanes own R columns of a 64R-column strip.  R = 2 halves
-// the window reads per site; R = 1 is used for wide discs (large register
-// rings) and for small batches, where twice the strips give twice the waves.
-// A wave's band height B trades parallelism (enough waves to fill 256 CUs
-// about 12 deep) against the 2m-row window overhead of each band, and never
-// goes below max(16, 2m) rows.
-inline int stream_band_rows(int n, int M, int TX, int nids) {
-    const int strips = (n + TX - 1) / TX;
-    const int64_t target_waves = 3072;
-    const int64_t have = (int64_t)strips * nids;
-    int64_t bands = (target_waves + have - 1) / have;
-    if (bands < 1) bands = 1;
-    int B = (int)((n + bands - 1) / bands);
-    const int bmin = M * 2 > 16 ? M * 2 : 16;
-    if (B < bmin) B = bmin;
-    if (B > n) B = n;
-    return B;
-}
-
-inline int stream_lanes_cols(int n, int M, int nids) {
-    if (M >= 24) return 1;
-    // waves available with R = 2 at the minimum band height
-    const int bmin = M * 2 > 16 ? M * 2 : 16;
-    const int64_t waves2 = (int64_t)((n + 127) / 128) * ((n + bmin - 1) / bmin) * nids;
-    return waves2 < 2048 ? 1 : 2;
-}
-
+// Streaming shape: lanes own R columns of a 64R-column strip (R = 2 halves
+// the window reads per site, R = 1 halves the register ring), and a wave's
+// band height B trades parallelism against the 2m-row window overhead of
+// each band.  The heuristic below aims at about 12 waves per CU with bands
+// of at least max(16, 2m) rows; the host's autotuner may override (R, B).
+// Every shape gives bit-identical results: each site sums the same window
+// sums in the same row order.
 template <int R2, int R, class TS, class TA, bool GAUSS>
-hipError_t stream_launch(const Group &g, const void *in, void *out, hipStream_t s) {
-    constexpr int M = Disc<R2>::M;
+hipError_t stream_launch(const Group &g, int B, const void *in, void *out, hipStream_t s) {
     constexpr int TX = 64 * R;
-    const int B = stream_band_rows(g.n, M, TX, g.nids);
     const int strips = (g.n + TX - 1) / TX;
     const int bands = (g.n + B - 1) / B;
     const int64_t nb = (int64_t)strips * bands * g.nids;
-    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (nb > 0x7fffffff || B < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
                        g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, B, strips, bands,
                        (int)nb);
@@ -58,13 +36,12 @@ hipError_t stream_launch(const Group &g, const void *in, void *out, hipStream_t 
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t s) {
     constexpr int M = Disc<R2>::M;
-    if constexpr (M >= 24) {
-        return stream_launch<R2, 1, TS, TA, GAUSS>(g, in, out, s);
-    } else {
-        if (stream_lanes_cols(g.n, M, g.nids) == 1)
-            return stream_launch<R2, 1, TS, TA, GAUSS>(g, in, out, s);
-        return stream_launch<R2, 2, TS, TA, GAUSS>(g, in, out, s);
-    }
+    int R = g.tune_R, B = g.tune_B;
+    if (R != 1 && R != 2) R = stream_lanes_cols(g.n, M, g.nids);
+    if (B < 1) B = stream_band_rows(g.n, M, 64 * R, g.nids);
+    (void)M;
+    if (R == 1) return stream_launch<R2, 1, TS, TA, GAUSS>(g, B, in, out, s);
+    return stream_launch<R2, 2, TS, TA, GAUSS>(g, B, in, out, s);
 }
 
 // Resident layout: one wave per band of kResB rows, lanes own one (n = 64)

@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "nlch.h"
@@ -221,6 +222,7 @@ struct Batch {
     DevBuf geo, ewf, ewd, sd, ids, partial;
     std::vector<Group> groups;           // launch groups
     std::vector<int> variant;            // per group
+    bool tuned = false;
     std::map<std::vector<uint8_t>, hipGraphExec_t> graphs;
     ~Batch() {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -306,7 +308,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     std::vector<uint8_t> key;
     append_bytes(key, dev);
     append_bytes(key, prec);
-    append_bytes(key, algo & 0x1ff);
+    append_bytes(key, algo & (0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_AUTOTUNE));
     append_bytes(key, n_models);
     append_bytes(key, n_samples);
     for (int i = 0; i < n_models; ++i) append_bytes(key, models[i]);
@@ -430,6 +432,66 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     return NLCH_OK;
 }
 
+// Autotuner of the streaming launch shape, cached per (device, precision,
+// disc, kernel, lattice, group size).
+struct TuneKey {
+    int dev, prec, R2, kernel, n, nids;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dev, prec, R2, kernel, n, nids) <
+               std::tie(o.dev, o.prec, o.R2, o.kernel, o.n, o.nids);
+    }
+};
+std::map<TuneKey, std::pair<int, int>> g_tuned;
+
+int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void *out,
+                   hipStream_t s) {
+    const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.nids};
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        g.tune_R = it->second.first;
+        g.tune_B = it->second.second;
+        return NLCH_OK;
+    }
+    const int bmin = g.m * 2 > 16 ? g.m * 2 : 16;
+    std::vector<std::pair<int, int>> cands;
+    for (int R = 1; R <= 2; ++R) {
+        const int strips = (g.n + 64 * R - 1) / (64 * R);
+        for (int B = bmin;; B *= 2) {
+            const int Bc = B < g.n ? B : g.n;
+            const int64_t waves = (int64_t)strips * ((g.n + Bc - 1) / Bc) * g.nids;
+            if (waves >= 128 || Bc == bmin || Bc == g.n) cands.push_back({R, Bc});
+            if (Bc >= g.n) break;
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::pair<int, int> pick{0, 0};
+    for (auto c : cands) {
+        g.tune_R = c.first;
+        g.tune_B = c.second;
+        hipError_t e = launch_rowrun_step(prec, acc64, g, in, out, s);  // warm-up
+        if (e != hipSuccess) continue;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) HIP_TRY(launch_rowrun_step(prec, acc64, g, in, out, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g.tune_R = pick.first;
+    g.tune_B = pick.second;
+    g_tuned[key] = pick;
+    return NLCH_OK;
+}
+
 hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
                        void *out, hipStream_t s) {
     if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s);
@@ -467,7 +529,8 @@ int enqueue_solve(Batch &b, int prec, bool acc64, int nsteps, void *state, void 
 }
 
 int check_algo_flags(int32_t algo) {
-    const int32_t known = 0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_NOGRAPH | NLCH_ALGO_CHECK_FINITE;
+    const int32_t known = 0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_NOGRAPH | NLCH_ALGO_CHECK_FINITE |
+                          NLCH_ALGO_AUTOTUNE;
     if (algo & ~known) return fail(NLCH_EINVAL, "unknown algorithm flags 0x%x", algo & ~known);
     const int base = algo & 0xff;
     if (base < NLCH_ALGO_AUTO || base > NLCH_ALGO_RESIDENT)
@@ -652,6 +715,15 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models, const nlch_samp
         HIP_TRY(hipStreamSynchronize(s));
         if (*ctx->counter_h)
             return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
+    }
+
+    if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            if (b->variant[gi] != kRowrun) continue;
+            rc = autotune_group(b->groups[gi], b->device, precision, acc64, state, scratch, s);
+            if (rc) return rc;
+        }
+        b->tuned = true;
     }
 
     if (algo & NLCH_ALGO_NOGRAPH)

@@ -54,7 +54,33 @@ struct Group {
     int32_t n, m, R2;
     int32_t kernel;
     int32_t model;
+    int32_t tune_R, tune_B;  // streaming shape (0 = heuristic)
 };
+
+// Heuristic streaming shape of the row-run kernel: lanes own R columns of a
+// 64R-column strip; a wave's band height B trades parallelism (about 12
+// waves per CU) against the 2m-row window overhead of each band, and is at
+// least max(16, 2m) rows.
+inline int stream_band_rows(int n, int M, int TX, int nids) {
+    const int strips = (n + TX - 1) / TX;
+    const int64_t target_waves = 3072;
+    const int64_t have = (int64_t)strips * nids;
+    int64_t bands = (target_waves + have - 1) / have;
+    if (bands < 1) bands = 1;
+    int B = (int)((n + bands - 1) / bands);
+    const int bmin = M * 2 > 16 ? M * 2 : 16;
+    if (B < bmin) B = bmin;
+    if (B > n) B = n;
+    return B;
+}
+
+inline int stream_lanes_cols(int n, int M, int nids) {
+    if (M >= 24) return 1;  // wide discs: keep the register ring small
+    // waves available with R = 2 at the minimum band height
+    const int bmin = M * 2 > 16 ? M * 2 : 16;
+    const int64_t waves2 = (int64_t)((n + 127) / 128) * ((n + bmin - 1) / bmin) * nids;
+    return waves2 < 2048 ? 1 : 2;
+}
 
 // Kernel variants.
 enum Variant { kDirect = 1, kRowrun = 2, kResident = 3 };

@@ -34,6 +34,7 @@ NLCH_ALGO_RESIDENT = 3
 NLCH_ALGO_ACC64 = 0x100
 NLCH_ALGO_NOGRAPH = 0x200
 NLCH_ALGO_CHECK_FINITE = 0x400
+NLCH_ALGO_AUTOTUNE = 0x800
 
 NLCH_MFMC_MAX_K = 8
 NLCH_MFMC_MAX_POOL = 16

@@ -106,7 +106,7 @@ def test_step_argument_errors():
     md = _good_model()
     E = nlch.NLCH_EINVAL
     assert _err(nlch.nlch_step, md, 7, 0, 4096, 8192) == E
-    assert _err(nlch.nlch_step, md, 1, 0x800, 4096, 8192) == E
+    assert _err(nlch.nlch_step, md, 1, 0x1000, 4096, 8192) == E
     assert _err(nlch.nlch_step, md, 1, nlch.NLCH_ALGO_RESIDENT, 4096, 8192) == E
     assert _err(nlch.nlch_step, md, 1, 0, 4096, 4096) == E           # aliasing
     assert _err(nlch.nlch_step, md, 1, 0, 4096, 4096 + 100) == E     # overlap

@@ -229,3 +229,28 @@ def test_mfmc_estimate_matches_oracle():
         for k in ("mean_mj", "var", "rho", "alpha"):
             np.testing.assert_allclose(got[k], ref[k], rtol=1e-11, atol=1e-15)
         np.testing.assert_allclose(got["mean_mjm1"][1:], ref["mean_mjm1"][1:], rtol=1e-13)
+
+
+def test_autotuned_shapes_give_identical_results():
+    """The streaming kernel's launch shape (columns per lane, band height) does
+    not change any result: every site sums the same window sums in the same
+    row order.  The autotuner times several shapes and keeps one."""
+    delta = 1.0 / 32
+    amp, sigma, _ = synth.gaussian_params(delta)
+    models = [synth.Model(256, delta, 1, amp, sigma, tau=0.01),
+              synth.Model(300, 16 / 300, 0, 1.0253 * 300 * 300 / 797, 0.0, tau=0.01),
+              synth.Model(1024, 1 / 32, 1, amp, sigma, tau=0.01)]
+    samples = [synth.Sample(0, 1.0, amp, "nuclei", 4, s, synth.draw_theta(synth.rng_for(4, s)))
+               for s in range(3)]
+    samples += [synth.Sample(1, 1.0, models[1].amp, "iid", 7, s) for s in range(2)]
+    samples += [synth.Sample(2, 1.0, amp, "nuclei", 4, 9, synth.draw_theta(synth.rng_for(4, 9)))]
+    w = synth.Workload("shapes", models, samples, 9, "f32")
+    a = DeviceBatch(w)
+    a.solve(nlch.NLCH_ALGO_ROWRUN)
+    b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_ROWRUN | nlch.NLCH_ALGO_AUTOTUNE)
+    b.reset()
+    b.solve(nlch.NLCH_ALGO_ROWRUN | nlch.NLCH_ALGO_AUTOTUNE)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.ooi, b.ooi)
