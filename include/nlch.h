@@ -162,6 +162,28 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models,
                      void *state, void *scratch, double *ooi_out,
                      void *hip_stream);
 
+/* nlch_solve_batch with the discrete energy trace (diagnostic; the energy of
+ * Sec. 2 with the nonlocal interaction term and the obstacle potential):
+ *   E_h(u) = h^2 [ 1/4 sum_i sum_{d in D} w_d (u_i - u_{i+d})^2
+ *                  + c_F/2 sum_i (1 - u_i^2) ],   w_d = h^2 gamma(h|d|),
+ * evaluated in FP64 on the stored states as h^2 [ 1/2 sum_i u_i L_i +
+ * c_F/2 sum_i (1 - u_i^2) ] with L_i the operator sum of the step (equal on
+ * the torus because the disc is symmetric); L_i is accumulated in the
+ * arithmetic of the step, the two sums in FP64.
+ * energy_out: device array of (nsteps + 1) * n_samples doubles, caller-owned;
+ * energy_out[k * n_samples + s] = E_h(u^k) of sample s, k = 0 (projected
+ * initial state) .. nsteps, with the sample's own c_F and kernel amplitude.
+ * The energy is reduced inside the step kernels; it costs one more operator
+ * evaluation per sample for k = nsteps (whose update goes to `scratch`, whose
+ * contents are unspecified afterwards) and, for the streaming kernels, one
+ * small reduction launch per step.  All other arguments, results and errors
+ * are those of nlch_solve_batch; energy_out == NULL is NLCH_EINVAL. */
+int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
+                            const nlch_sample *samples, int64_t n_samples,
+                            int32_t nsteps, int32_t precision, int32_t algo,
+                            void *state, void *scratch, double *ooi_out,
+                            double *energy_out, void *hip_stream);
+
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
  * y_dev[j]: device pointer to the outputs of model j+1, the output for
  * parameter draw i at y_dev[j][i * y_stride] for i < m[j] (draws shared

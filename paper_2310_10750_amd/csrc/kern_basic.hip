@@ -8,6 +8,11 @@
 //    difference form  Lsum = sum_{d != 0} e_d (u_i - u_{i+d})  (eq.
 //    nonl_operator with nodal quadrature), then the projected update.  Halo
 //    tile staged in LDS; any horizon up to kMaxM.
+//  * k_energy_final: per sample, the step kernels' workgroup partial sums of
+//    sum u Lsum and sum (1 - u^2) in workgroup order -> the discrete energy
+//    E_h(u) = h^2 [ 1/2 sum_i u_i L_i + c_F/2 sum_i (1 - u_i^2) ] (the energy of
+//    Sec. 2 with the nonlocal interaction; 1/4 sum_i sum_d w_d (u_i - u_{i+d})^2
+//    equals 1/2 sum_i u_i L_i on the torus because the disc is symmetric).
 #include "nlch_device.h"
 
 namespace nlch {
@@ -90,15 +95,16 @@ __global__ __launch_bounds__(64) void k_ooi_final(const int32_t *__restrict__ id
     ooi[2 * sidx + 1] = 0.5 * (1.0 + mean);
 }
 
-constexpr int kDirTX = 64, kDirTY = 16, kDirThreads = 256;
+constexpr int kDirThreads = 256;
 
 template <class TS, class TA, bool GAUSS>
 __global__ __launch_bounds__(kDirThreads) void k_direct(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const TA *__restrict__ ew,
     const TS *__restrict__ in, TS *__restrict__ out, int tiles_x,
-    int tiles_per_sample, int nblocks) {
+    int tiles_per_sample, int nblocks, double *__restrict__ epart) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kDirThreads / 64];
     TA *tile = reinterpret_cast<TA *>(smem_raw);
     const int n = geo->n, m = geo->m;
     const int b = xcd_remap(blockIdx.x, nblocks);
@@ -122,6 +128,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(
     const TA a = coef_a<TA>(d), bb = coef_b<TA>(d);
     const TA *ewm = ew + geo->e_off;
     const int lx = threadIdx.x & 63;
+    double e_ul = 0.0, e_pot = 0.0;
     for (int ly = threadIdx.x >> 6; ly < kDirTY; ly += kDirThreads / 64) {
         const int y = y0 + ly, x = x0 + lx;
         const TA *cen = tile + (ly + m) * W + lx + m;
@@ -141,7 +148,44 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(
                 }
             }
         }
-        if (y < n && x < n) dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(uc, acc, a, bb));
+        if (y < n && x < n) {
+            dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(uc, acc, a, bb));
+            e_ul += (double)uc * (double)acc;
+            e_pot += 1.0 - (double)uc * (double)uc;
+        }
+    }
+    if (epart) {
+        e_ul = block_sum(e_ul, red);
+        e_pot = block_sum(e_pot, red);
+        if (threadIdx.x == 0) {
+            epart[2 * (int64_t)b] = e_ul;
+            epart[2 * (int64_t)b + 1] = e_pot;
+        }
+    }
+}
+
+// One wave per sample of the group: lane l sums partials l, l + 64, ... in
+// order, then a fixed shuffle tree (the result does not depend on timing).
+__global__ __launch_bounds__(64) void k_energy_final(const SampleDesc *__restrict__ sd,
+                                                     const int32_t *__restrict__ ids,
+                                                     int per_sample,
+                                                     const double *__restrict__ epart,
+                                                     double *__restrict__ energy) {
+    const int j = blockIdx.x;
+    const double *p = epart + 2 * (int64_t)j * per_sample;
+    double s_ul = 0.0, s_pot = 0.0;
+    for (int i = threadIdx.x; i < per_sample; i += 64) {
+        s_ul += p[2 * i];
+        s_pot += p[2 * i + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s_ul += __shfl_xor(s_ul, o, 64);
+        s_pot += __shfl_xor(s_pot, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        const int64_t sidx = ids[j];
+        const SampleDesc d = sd[sidx];
+        energy[sidx] = d.e_int * s_ul + d.e_pot * s_pot;
     }
 }
 
@@ -231,7 +275,8 @@ template <>
 const double *ew_for<double>(const Group &g) { return g.ewd; }
 
 template <class TS, class TA>
-static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStream_t s) {
+static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStream_t s,
+                               double *epart) {
     const int tiles_x = (g.n + kDirTX - 1) / kDirTX;
     const int tiles_y = (g.n + kDirTY - 1) / kDirTY;
     const int tps = tiles_x * tiles_y;
@@ -244,29 +289,37 @@ static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStr
         hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
-                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb);
+                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb, epart);
     } else {
         auto f = k_direct<TS, TA, false>;
         hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
         hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
-                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb);
+                           (const TS *)in, (TS *)out, tiles_x, tps, (int)nb, epart);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_direct_step(int prec, bool acc64, const Group &g, const void *in,
-                              void *out, hipStream_t s) {
+                              void *out, hipStream_t s, double *epart) {
     switch (prec) {
         case kF64:
-            return direct_typed<double, double>(g, in, out, s);
+            return direct_typed<double, double>(g, in, out, s, epart);
         case kF32:
-            return acc64 ? direct_typed<float, double>(g, in, out, s)
-                         : direct_typed<float, float>(g, in, out, s);
+            return acc64 ? direct_typed<float, double>(g, in, out, s, epart)
+                         : direct_typed<float, float>(g, in, out, s, epart);
         default:
-            return acc64 ? direct_typed<half_t, double>(g, in, out, s)
-                         : direct_typed<half_t, float>(g, in, out, s);
+            return acc64 ? direct_typed<half_t, double>(g, in, out, s, epart)
+                         : direct_typed<half_t, float>(g, in, out, s, epart);
     }
+}
+
+hipError_t launch_energy_final(const Group &g, const double *epart, int per_sample,
+                               double *energy, hipStream_t s) {
+    if (per_sample < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_energy_final, dim3((unsigned)g.nids), dim3(64), 0, s, g.sd, g.ids,
+                       per_sample, epart, energy);
+    return hipGetLastError();
 }
 
 }  // namespace nlch

@@ -21,7 +21,8 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // Every shape gives bit-identical results: each site sums the same window
 // sums in the same row order.
 template <int R2, int R, class TS, class TA, bool GAUSS>
-hipError_t stream_launch(const Group &g, int B, const void *in, void *out, hipStream_t s) {
+hipError_t stream_launch(const Group &g, int B, const void *in, void *out, hipStream_t s,
+                         double *epart) {
     constexpr int TX = 64 * R;
     const int strips = (g.n + TX - 1) / TX;
     const int bands = (g.n + B - 1) / B;
@@ -29,19 +30,17 @@ hipError_t stream_launch(const Group &g, int B, const void *in, void *out, hipSt
     if (nb > 0x7fffffff || B < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
                        g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, B, strips, bands,
-                       (int)nb);
+                       (int)nb, epart);
     return hipGetLastError();
 }
 
 template <int R2, class TS, class TA, bool GAUSS>
-hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t s) {
-    constexpr int M = Disc<R2>::M;
-    int R = g.tune_R, B = g.tune_B;
-    if (R != 1 && R != 2) R = stream_lanes_cols(g.n, M, g.nids);
-    if (B < 1) B = stream_band_rows(g.n, M, 64 * R, g.nids);
-    (void)M;
-    if (R == 1) return stream_launch<R2, 1, TS, TA, GAUSS>(g, B, in, out, s);
-    return stream_launch<R2, 2, TS, TA, GAUSS>(g, B, in, out, s);
+hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t s,
+                         double *epart) {
+    int R = 1, B = 1, per_sample = 0;
+    stream_shape(g, &R, &B, &per_sample);
+    if (R == 1) return stream_launch<R2, 1, TS, TA, GAUSS>(g, B, in, out, s, epart);
+    return stream_launch<R2, 2, TS, TA, GAUSS>(g, B, in, out, s, epart);
 }
 
 // Resident layout: one wave per band of kResB rows, lanes own one (n = 64)
@@ -50,25 +49,30 @@ constexpr int kResB = 16;
 
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
-                           hipStream_t s) {
+                           hipStream_t s, double *energy, int64_t estride) {
     constexpr int M = Disc<R2>::M;
     const int threads = 64 * (g.n / kResB);
     const size_t lds = resident_lds_bytes(g.n, M, kResB, sizeof(TS), sizeof(TA));
     if ((g.n != 64 && g.n != 128) || lds > kLdsBytes - 1024) return hipErrorInvalidValue;
     auto go = [&](auto f) {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(kLdsBytes - 1024));
-            attr = true;
-        }
+        // per kernel (every instantiation has the same pointer type, so no
+        // per-type static flag here)
+        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kLdsBytes - 1024));
         hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(threads), lds, s, g.sd, g.ids,
-                           g.geo, (TS *)state, nsteps, ooi);
+                           g.geo, (TS *)state, nsteps, ooi, energy, estride);
     };
-    if (g.n == 64)
-        go(k_resident<R2, 64, kResB, TS, TA, GAUSS>);
-    else
-        go(k_resident<R2, 128, kResB, TS, TA, GAUSS>);
+    if (energy) {
+        if (g.n == 64)
+            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true>);
+        else
+            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true>);
+    } else {
+        if (g.n == 64)
+            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false>);
+        else
+            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false>);
+    }
     return hipGetLastError();
 }
 
@@ -95,11 +99,12 @@ bool resident_has_typed(int R2, int n) {
 }
 
 template <class TS, class TA>
-hipError_t rowrun_step_typed(const Group &g, const void *in, void *out, hipStream_t s) {
-#define NLCH_X(v)                                                       \
-    if (g.R2 == v)                                                      \
-        return g.kernel == 1 ? rowrun_launch<v, TS, TA, true>(g, in, out, s) \
-                             : rowrun_launch<v, TS, TA, false>(g, in, out, s);
+hipError_t rowrun_step_typed(const Group &g, const void *in, void *out, hipStream_t s,
+                             double *epart) {
+#define NLCH_X(v)                                                              \
+    if (g.R2 == v)                                                             \
+        return g.kernel == 1 ? rowrun_launch<v, TS, TA, true>(g, in, out, s, epart) \
+                             : rowrun_launch<v, TS, TA, false>(g, in, out, s, epart);
     NLCH_ROWRUN_R2_LIST(NLCH_X)
 #undef NLCH_X
     return hipErrorInvalidValue;
@@ -107,11 +112,14 @@ hipError_t rowrun_step_typed(const Group &g, const void *in, void *out, hipStrea
 
 template <class TS, class TA>
 hipError_t resident_typed(const Group &g, void *state, int nsteps, double *ooi,
-                          hipStream_t s) {
-#define NLCH_X(v)                                                                   \
-    if (g.R2 == v)                                                                  \
-        return g.kernel == 1 ? resident_launch<v, TS, TA, true>(g, state, nsteps, ooi, s) \
-                             : resident_launch<v, TS, TA, false>(g, state, nsteps, ooi, s);
+                          hipStream_t s, double *energy, int64_t estride) {
+#define NLCH_X(v)                                                                      \
+    if (g.R2 == v)                                                                     \
+        return g.kernel == 1                                                           \
+                   ? resident_launch<v, TS, TA, true>(g, state, nsteps, ooi, s, energy, \
+                                                      estride)                         \
+                   : resident_launch<v, TS, TA, false>(g, state, nsteps, ooi, s, energy, \
+                                                       estride);
     NLCH_RESIDENT_R2_LIST(NLCH_X)
 #undef NLCH_X
     return hipErrorInvalidValue;
@@ -125,11 +133,11 @@ hipError_t resident_typed(const Group &g, void *state, int nsteps, double *ooi,
     bool rowrun_has_##SUFFIX(int R2) { return rowrun_has_typed<TS, TA>(R2); }               \
     bool resident_has_##SUFFIX(int R2, int n) { return resident_has_typed<TS, TA>(R2, n); } \
     hipError_t rowrun_step_##SUFFIX(const Group &g, const void *in, void *out,              \
-                                    hipStream_t s) {                                        \
-        return rowrun_step_typed<TS, TA>(g, in, out, s);                                    \
+                                    hipStream_t s, double *epart) {                         \
+        return rowrun_step_typed<TS, TA>(g, in, out, s, epart);                             \
     }                                                                                       \
     hipError_t resident_##SUFFIX(const Group &g, void *state, int nsteps, double *ooi,      \
-                                 hipStream_t s) {                                           \
-        return resident_typed<TS, TA>(g, state, nsteps, ooi, s);                            \
+                                 hipStream_t s, double *energy, int64_t estride) {          \
+        return resident_typed<TS, TA>(g, state, nsteps, ooi, s, energy, estride);           \
     }                                                                                       \
     }

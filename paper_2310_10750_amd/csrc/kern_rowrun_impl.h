@@ -137,7 +137,8 @@ template <int R2, int R, class TS, class TA, bool GAUSS>
 __global__ __launch_bounds__(64) void k_stream(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const TS *__restrict__ in,
-    TS *__restrict__ out, int B, int strips, int bands, int nblocks) {
+    TS *__restrict__ out, int B, int strips, int bands, int nblocks,
+    double *__restrict__ epart) {
     constexpr int M = Disc<R2>::M, P = Disc<R2>::P;
     constexpr int TX = 64 * R;
     constexpr int TW = TX + 2 * M;
@@ -183,6 +184,10 @@ __global__ __launch_bounds__(64) void k_stream(
     for (int i = 0; i < P; ++i)
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[i][c] = TA(-0.0);
+    // energy partial sums of the input state (only with epart): sum u Lsum
+    // and sum (1 - u^2) over this lane's outputs in the arithmetic type, then
+    // across the wave in FP64
+    TA e_ul = TA(0), e_pot = TA(0);
 
     for (int pb = 0; pb < rows; pb += P) {
 #pragma unroll
@@ -228,13 +233,30 @@ __global__ __launch_bounds__(64) void k_stream(
                         const int x = x0 + c0 + c;
                         const TA u = to_acc<TA>(cen[c]);
                         const TA lsum = ce * u - acc[done][c];
-                        if (x < n)
+                        if (x < n) {
                             dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                            if (epart) {
+                                e_ul += u * lsum;
+                                e_pot += TA(1) - u * u;
+                            }
+                        }
                     }
                 }
 #pragma unroll
                 for (int c = 0; c < R; ++c) acc[done][c] = TA(-0.0);
             }
+        }
+    }
+    if (epart) {
+        // fixed shuffle tree: the partials do not depend on timing
+        double s_ul = (double)e_ul, s_pot = (double)e_pot;
+        for (int o = 32; o > 0; o >>= 1) {
+            s_ul += __shfl_xor(s_ul, o, 64);
+            s_pot += __shfl_xor(s_pot, o, 64);
+        }
+        if (lane == 0) {
+            epart[2 * (int64_t)bidx] = s_ul;
+            epart[2 * (int64_t)bidx + 1] = s_pot;
         }
     }
 }
@@ -267,11 +289,11 @@ __host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, siz
     return (size_t)n * resident_row_stride(n, M) * ts + 2 * (size_t)(n / B) * M * n * ta;
 }
 
-template <int R2, int N, int B, class TS, class TA, bool GAUSS>
+template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY>
 __global__ __launch_bounds__(512) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
-    double *__restrict__ ooi) {
+    double *__restrict__ ooi, double *__restrict__ energy, int64_t estride) {
     // The lattice size is a compile-time constant so that every LDS offset
     // below is an instruction immediate rather than a register.
     constexpr int M = Disc<R2>::M;
@@ -317,7 +339,10 @@ __global__ __launch_bounds__(512) void k_resident(
             st[q][c] = clamp1(v);
         }
 
-    for (int step = 0; step < nsteps; ++step) {
+    // With the energy trace, one more pass evaluates E_h(u^nsteps); its
+    // update is discarded and the state is written back from the LDS copy.
+    const int passes = nsteps + (ENERGY ? 1 : 0);
+    for (int step = 0; step < passes; ++step) {
         // Publish the state (and its periodic column halo) to LDS.  A column
         // without a halo copy writes its value twice to the same place.
 #pragma unroll
@@ -380,17 +405,33 @@ __global__ __launch_bounds__(512) void k_resident(
                 acc[B + j][c] += xup[((size_t)bup * M + j) * n + x];
             }
         }
+        // (energy trace) E_h of the state this pass started from, from the
+        // per-site terms u Lsum and 1 - u^2 accumulated in FP64
+        double e_ul = 0.0, e_pot = 0.0;
 #pragma unroll
         for (int q = 0; q < B; ++q)
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 const TA u = st[q][c];
                 const TA lsum = ce * u - acc[M + q][c];
+                if constexpr (ENERGY) {
+                    if (xb + c < n) {
+                        e_ul += (double)u * (double)lsum;
+                        e_pot += 1.0 - (double)u * (double)u;
+                    }
+                }
                 st[q][c] = to_acc<TA>(to_store<TS>(update<TA>(u, lsum, a, bcoef)));
             }
+        if constexpr (ENERGY) {
+            e_ul = block_sum(e_ul, red);
+            e_pot = block_sum(e_pot, red);
+            if (threadIdx.x == 0)
+                energy[(int64_t)step * estride + sidx] = d.e_int * e_ul + d.e_pot * e_pot;
+        }
     }
 
-    // Write back and reduce the output of interest in FP64.
+    // Write back and reduce the output of interest in FP64 (with the energy
+    // trace the last pass's update is dropped: u^nsteps is the LDS copy).
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < B; ++q)
@@ -398,8 +439,9 @@ __global__ __launch_bounds__(512) void k_resident(
         for (int c = 0; c < R; ++c) {
             const int x = xb + c;
             if (x < n) {
-                g_state[(int64_t)(y0 + q) * n + x] = to_store<TS>(st[q][c]);
-                part += (double)st[q][c];
+                const TA v = ENERGY ? to_acc<TA>(lds[(y0 + q) * TW + M + x]) : st[q][c];
+                g_state[(int64_t)(y0 + q) * n + x] = to_store<TS>(v);
+                part += (double)v;
             }
         }
     const double tot = block_sum(part, red);

@@ -23,9 +23,10 @@ namespace nlch {
 #define NLCH_DECL(SUF)                                                                   \
     bool rowrun_has_##SUF(int R2);                                                       \
     bool resident_has_##SUF(int R2, int n);                                              \
-    hipError_t rowrun_step_##SUF(const Group &g, const void *in, void *out, hipStream_t s); \
+    hipError_t rowrun_step_##SUF(const Group &g, const void *in, void *out, hipStream_t s, \
+                                 double *epart);                                         \
     hipError_t resident_##SUF(const Group &g, void *state, int nsteps, double *ooi,      \
-                              hipStream_t s);
+                              hipStream_t s, double *energy, int64_t estride);
 NLCH_DECL(f64)
 NLCH_DECL(f32)
 NLCH_DECL(f16)
@@ -51,20 +52,20 @@ bool resident_supported(int prec, bool acc64, int R2, int, int n) {
 }
 
 hipError_t launch_rowrun_step(int prec, bool, const Group &g, const void *in, void *out,
-                              hipStream_t s) {
+                              hipStream_t s, double *epart) {
     switch (prec) {
-        case kF64: return rowrun_step_f64(g, in, out, s);
-        case kF32: return rowrun_step_f32(g, in, out, s);
-        default: return rowrun_step_f16(g, in, out, s);
+        case kF64: return rowrun_step_f64(g, in, out, s, epart);
+        case kF32: return rowrun_step_f32(g, in, out, s, epart);
+        default: return rowrun_step_f16(g, in, out, s, epart);
     }
 }
 
 hipError_t launch_resident(int prec, bool, const Group &g, void *state, int nsteps,
-                           double *ooi, hipStream_t s) {
+                           double *ooi, hipStream_t s, double *energy, int64_t estride) {
     switch (prec) {
-        case kF64: return resident_f64(g, state, nsteps, ooi, s);
-        case kF32: return resident_f32(g, state, nsteps, ooi, s);
-        default: return resident_f16(g, state, nsteps, ooi, s);
+        case kF64: return resident_f64(g, state, nsteps, ooi, s, energy, estride);
+        case kF32: return resident_f32(g, state, nsteps, ooi, s, energy, estride);
+        default: return resident_f16(g, state, nsteps, ooi, s, energy, estride);
     }
 }
 
@@ -220,6 +221,8 @@ struct Batch {
     std::vector<uint8_t> key;
     int device = -1;
     DevBuf geo, ewf, ewd, sd, ids, partial;
+    DevBuf epart;                        // energy partial sums (allocated on demand)
+    size_t epart_cap = 0;                // doubles in epart
     std::vector<Group> groups;           // launch groups
     std::vector<int> variant;            // per group
     bool tuned = false;
@@ -372,6 +375,9 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         d.b = c.b;
         d.af = rne_f32(c.a);
         d.bf = rne_f32(c.b);
+        const double h2 = 1.0 / ((double)d.n * d.n);
+        d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
+        d.e_pot = 0.5 * h2 * sm.c_F;
     }
     // Groups: per model, samples in batch order.
     std::vector<std::vector<int32_t>> per_model(n_models);
@@ -493,19 +499,61 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
 }
 
 hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
-                       void *out, hipStream_t s) {
-    if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s);
-    return launch_direct_step(prec, acc64, g, in, out, s);
+                       void *out, hipStream_t s, double *epart = nullptr) {
+    if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s, epart);
+    return launch_direct_step(prec, acc64, g, in, out, s, epart);
 }
 
-// Enqueues a whole batch solve on stream s.
+// Workgroups one sample of a streaming group occupies per step launch.
+int step_blocks_per_sample(int variant, const Group &g) {
+    if (variant == kRowrun) {
+        int R = 1, B = 1, ps = 0;
+        stream_shape(g, &R, &B, &ps);
+        return ps;
+    }
+    return direct_tiles(g.n);
+}
+
+// Energy partial-sum area of streaming group gi (after ensure_epart).
+double *group_epart(Batch &b, size_t gi) {
+    size_t off = 0;
+    for (size_t i = 0; i < gi; ++i)
+        if (b.variant[i] != kResident)
+            off += 2 * (size_t)step_blocks_per_sample(b.variant[i], b.groups[i]) * b.groups[i].nids;
+    return reinterpret_cast<double *>(b.epart.p) + off;
+}
+
+int ensure_epart(Batch &b) {
+    size_t need = 2;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi)
+        if (b.variant[gi] != kResident)
+            need += 2 * (size_t)step_blocks_per_sample(b.variant[gi], b.groups[gi]) *
+                    b.groups[gi].nids;
+    if (need <= b.epart_cap) return NLCH_OK;
+    if (b.epart.p) {
+        HIP_TRY(hipDeviceSynchronize());  // a queued graph may still read the old area
+        HIP_TRY(hipFree(b.epart.p));
+        b.epart.p = nullptr;
+        b.epart_cap = 0;
+        for (auto &kv : b.graphs) (void)hipGraphExecDestroy(kv.second);
+        b.graphs.clear();
+    }
+    HIP_TRY(hipMalloc(&b.epart.p, sizeof(double) * need));
+    b.epart_cap = need;
+    return NLCH_OK;
+}
+
+// Enqueues a whole batch solve on stream s.  With `energy` (n_samples-strided
+// rows k = 0..nsteps), every step launch also reduces E_h of its input state,
+// and one more launch per streaming group evaluates E_h(u^nsteps) (its update
+// goes to `scratch` and is dropped).
 int enqueue_solve(Batch &b, int prec, bool acc64, int nsteps, void *state, void *scratch,
-                  double *ooi, hipStream_t s) {
+                  double *ooi, double *energy, int64_t estride, hipStream_t s) {
     bool any_stream = false;
     for (size_t gi = 0; gi < b.groups.size(); ++gi) {
         const Group &g = b.groups[gi];
         if (b.variant[gi] == kResident) {
-            HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, s));
+            HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, s, energy, estride));
         } else {
             any_stream = true;
         }
@@ -516,12 +564,27 @@ int enqueue_solve(Batch &b, int prec, bool acc64, int nsteps, void *state, void 
     void *buf1 = (buf0 == state) ? scratch : state;
     for (size_t gi = 0; gi < b.groups.size(); ++gi)
         if (b.variant[gi] != kResident) HIP_TRY(launch_project(prec, b.groups[gi], state, buf0, s));
+    auto step_all = [&](int k, const void *in, void *out) -> int {
+        for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+            if (b.variant[gi] == kResident) continue;
+            const Group &g = b.groups[gi];
+            double *ep = energy ? group_epart(b, gi) : nullptr;
+            HIP_TRY(launch_step(b.variant[gi], prec, acc64, g, in, out, s, ep));
+            if (energy)
+                HIP_TRY(launch_energy_final(g, ep, step_blocks_per_sample(b.variant[gi], g),
+                                            energy + (int64_t)k * estride, s));
+        }
+        return NLCH_OK;
+    };
     void *cur = buf0, *nxt = buf1;
     for (int k = 0; k < nsteps; ++k) {
-        for (size_t gi = 0; gi < b.groups.size(); ++gi)
-            if (b.variant[gi] != kResident)
-                HIP_TRY(launch_step(b.variant[gi], prec, acc64, b.groups[gi], cur, nxt, s));
+        int rc = step_all(k, cur, nxt);
+        if (rc) return rc;
         std::swap(cur, nxt);
+    }
+    if (energy) {
+        int rc = step_all(nsteps, state, scratch);
+        if (rc) return rc;
     }
     for (size_t gi = 0; gi < b.groups.size(); ++gi)
         if (b.variant[gi] != kResident) HIP_TRY(launch_ooi(prec, b.groups[gi], state, ooi, 2, s));
@@ -540,11 +603,139 @@ int check_algo_flags(int32_t algo) {
 
 }  // namespace
 
+// nlch_solve_batch and nlch_solve_batch_energy (energy_out nullable here).
+static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sample *samples,
+                      int64_t n_samples, int32_t nsteps, int32_t precision, int32_t algo,
+                      void *state, void *scratch, double *ooi_out, double *energy_out,
+                      void *hip_stream) {
+    if (!models || n_models < 1) return fail(NLCH_EINVAL, "need at least one model");
+    if (!samples || n_samples < 1) return fail(NLCH_EINVAL, "need at least one sample");
+    if (n_samples > (int64_t)1 << 30) return fail(NLCH_EINVAL, "too many samples");
+    if (nsteps < 0) return fail(NLCH_EINVAL, "nsteps must be >= 0");
+    if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
+        return fail(NLCH_EINVAL, "unknown precision %d", precision);
+    int rc = check_algo_flags(algo);
+    if (rc) return rc;
+    if (!state || !ooi_out) return fail(NLCH_EINVAL, "state and ooi_out must be non-NULL");
+    std::vector<ModelInfo> mi((size_t)n_models);
+    for (int i = 0; i < n_models; ++i) {
+        char what[48];
+        snprintf(what, sizeof(what), "model %d", i);
+        rc = analyze_model(models[i], mi[i], what);
+        if (rc) return rc;
+    }
+    // Samples: indices, parameters, non-overlapping states.
+    std::vector<std::pair<int64_t, int64_t>> extents((size_t)n_samples);
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const nlch_sample &sm = samples[s];
+        if (sm.model < 0 || sm.model >= n_models)
+            return fail(NLCH_EINVAL, "sample %lld: model index %d out of range", (long long)s,
+                        sm.model);
+        if (sm.reserved != 0)
+            return fail(NLCH_EINVAL, "sample %lld: reserved field must be 0", (long long)s);
+        if (!finite_pos(sm.c_F) || !finite_pos(sm.kernel_amp))
+            return fail(NLCH_EINVAL, "sample %lld: c_F and kernel_amp must be > 0", (long long)s);
+        if (sm.offset < 0) return fail(NLCH_EINVAL, "sample %lld: negative offset", (long long)s);
+        const int64_t nn = (int64_t)models[sm.model].n * models[sm.model].n;
+        extents[(size_t)s] = {sm.offset, sm.offset + nn};
+        Coef c;
+        char what[48];
+        snprintf(what, sizeof(what), "sample %lld", (long long)s);
+        rc = sample_coef(models[sm.model], mi[sm.model], sm.c_F, sm.kernel_amp, c, what);
+        if (rc) return rc;
+    }
+    std::sort(extents.begin(), extents.end());
+    for (size_t i = 1; i < extents.size(); ++i)
+        if (extents[i].first < extents[i - 1].second)
+            return fail(NLCH_EINVAL, "sample states overlap in the state buffer");
+    // Kernel variant per model (host decision, before any device work).
+    const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64;
+    std::vector<char> used((size_t)n_models, 0);
+    for (int64_t s = 0; s < n_samples; ++s) used[(size_t)samples[s].model] = 1;
+    bool need_scratch = false;
+    for (int i = 0; i < n_models; ++i) {
+        if (!used[(size_t)i]) continue;
+        int variant = 0;
+        rc = choose_variant(algo & 0xff, precision, acc64, mi[i], models[i], true, &variant);
+        if (rc) return rc;
+        need_scratch |= (variant != kResident);
+    }
+    if (need_scratch && !scratch)
+        return fail(NLCH_EINVAL, "scratch must be non-NULL unless every sample runs RESIDENT");
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *ctx = nullptr;
+    rc = dev_ctx(&ctx);
+    if (rc) return rc;
+    Batch *b = nullptr;
+    rc = get_batch(models, n_models, mi, samples, n_samples, precision, algo, true, &b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    if (algo & NLCH_ALGO_CHECK_FINITE) {
+        HIP_TRY(hipMemsetAsync(ctx->counter, 0, sizeof(unsigned int), s));
+        for (const Group &g : b->groups)
+            HIP_TRY(launch_count_nonfinite(precision, g, state, ctx->counter, s));
+        HIP_TRY(hipMemcpyAsync(ctx->counter_h, ctx->counter, sizeof(unsigned int),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*ctx->counter_h)
+            return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
+    }
+
+    if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            if (b->variant[gi] != kRowrun) continue;
+            rc = autotune_group(b->groups[gi], b->device, precision, acc64, state, scratch, s);
+            if (rc) return rc;
+        }
+        b->tuned = true;
+    }
+
+    if (energy_out) {
+        rc = ensure_epart(*b);
+        if (rc) return rc;
+    }
+
+    if (algo & NLCH_ALGO_NOGRAPH)
+        return enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, energy_out,
+                             n_samples, s);
+
+    std::vector<uint8_t> gk;
+    append_bytes(gk, state);
+    append_bytes(gk, scratch);
+    append_bytes(gk, ooi_out);
+    append_bytes(gk, energy_out);
+    append_bytes(gk, nsteps);
+    auto it = b->graphs.find(gk);
+    if (it == b->graphs.end()) {
+        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+        rc = enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, energy_out,
+                           n_samples, ctx->capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail(NLCH_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail(NLCH_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        it = b->graphs.emplace(gk, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s));
+    return NLCH_OK;
+}
+
 // --------------------------------------------------------------------- ABI --
 
 extern "C" {
 
-int nlch_version(void) { return 2; }
+int nlch_version(void) { return 3; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 
@@ -642,119 +833,17 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
 int nlch_solve_batch(const nlch_model *models, int32_t n_models, const nlch_sample *samples,
                      int64_t n_samples, int32_t nsteps, int32_t precision, int32_t algo,
                      void *state, void *scratch, double *ooi_out, void *hip_stream) {
-    if (!models || n_models < 1) return fail(NLCH_EINVAL, "need at least one model");
-    if (!samples || n_samples < 1) return fail(NLCH_EINVAL, "need at least one sample");
-    if (n_samples > (int64_t)1 << 30) return fail(NLCH_EINVAL, "too many samples");
-    if (nsteps < 0) return fail(NLCH_EINVAL, "nsteps must be >= 0");
-    if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
-        return fail(NLCH_EINVAL, "unknown precision %d", precision);
-    int rc = check_algo_flags(algo);
-    if (rc) return rc;
-    if (!state || !ooi_out) return fail(NLCH_EINVAL, "state and ooi_out must be non-NULL");
-    std::vector<ModelInfo> mi((size_t)n_models);
-    for (int i = 0; i < n_models; ++i) {
-        char what[48];
-        snprintf(what, sizeof(what), "model %d", i);
-        rc = analyze_model(models[i], mi[i], what);
-        if (rc) return rc;
-    }
-    // Samples: indices, parameters, non-overlapping states.
-    std::vector<std::pair<int64_t, int64_t>> extents((size_t)n_samples);
-    for (int64_t s = 0; s < n_samples; ++s) {
-        const nlch_sample &sm = samples[s];
-        if (sm.model < 0 || sm.model >= n_models)
-            return fail(NLCH_EINVAL, "sample %lld: model index %d out of range", (long long)s,
-                        sm.model);
-        if (sm.reserved != 0)
-            return fail(NLCH_EINVAL, "sample %lld: reserved field must be 0", (long long)s);
-        if (!finite_pos(sm.c_F) || !finite_pos(sm.kernel_amp))
-            return fail(NLCH_EINVAL, "sample %lld: c_F and kernel_amp must be > 0", (long long)s);
-        if (sm.offset < 0) return fail(NLCH_EINVAL, "sample %lld: negative offset", (long long)s);
-        const int64_t nn = (int64_t)models[sm.model].n * models[sm.model].n;
-        extents[(size_t)s] = {sm.offset, sm.offset + nn};
-        Coef c;
-        char what[48];
-        snprintf(what, sizeof(what), "sample %lld", (long long)s);
-        rc = sample_coef(models[sm.model], mi[sm.model], sm.c_F, sm.kernel_amp, c, what);
-        if (rc) return rc;
-    }
-    std::sort(extents.begin(), extents.end());
-    for (size_t i = 1; i < extents.size(); ++i)
-        if (extents[i].first < extents[i - 1].second)
-            return fail(NLCH_EINVAL, "sample states overlap in the state buffer");
-    // Kernel variant per model (host decision, before any device work).
-    const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64;
-    std::vector<char> used((size_t)n_models, 0);
-    for (int64_t s = 0; s < n_samples; ++s) used[(size_t)samples[s].model] = 1;
-    bool need_scratch = false;
-    for (int i = 0; i < n_models; ++i) {
-        if (!used[(size_t)i]) continue;
-        int variant = 0;
-        rc = choose_variant(algo & 0xff, precision, acc64, mi[i], models[i], true, &variant);
-        if (rc) return rc;
-        need_scratch |= (variant != kResident);
-    }
-    if (need_scratch && !scratch)
-        return fail(NLCH_EINVAL, "scratch must be non-NULL unless every sample runs RESIDENT");
+    return solve_impl(models, n_models, samples, n_samples, nsteps, precision, algo, state,
+                      scratch, ooi_out, nullptr, hip_stream);
+}
 
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevCtx *ctx = nullptr;
-    rc = dev_ctx(&ctx);
-    if (rc) return rc;
-    Batch *b = nullptr;
-    rc = get_batch(models, n_models, mi, samples, n_samples, precision, algo, true, &b);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)hip_stream;
-
-    if (algo & NLCH_ALGO_CHECK_FINITE) {
-        HIP_TRY(hipMemsetAsync(ctx->counter, 0, sizeof(unsigned int), s));
-        for (const Group &g : b->groups)
-            HIP_TRY(launch_count_nonfinite(precision, g, state, ctx->counter, s));
-        HIP_TRY(hipMemcpyAsync(ctx->counter_h, ctx->counter, sizeof(unsigned int),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (*ctx->counter_h)
-            return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
-    }
-
-    if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
-        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-            if (b->variant[gi] != kRowrun) continue;
-            rc = autotune_group(b->groups[gi], b->device, precision, acc64, state, scratch, s);
-            if (rc) return rc;
-        }
-        b->tuned = true;
-    }
-
-    if (algo & NLCH_ALGO_NOGRAPH)
-        return enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, s);
-
-    std::vector<uint8_t> gk;
-    append_bytes(gk, state);
-    append_bytes(gk, scratch);
-    append_bytes(gk, ooi_out);
-    append_bytes(gk, nsteps);
-    auto it = b->graphs.find(gk);
-    if (it == b->graphs.end()) {
-        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
-        rc = enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, ctx->capture);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
-        if (rc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess)
-            return fail(NLCH_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess)
-            return fail(NLCH_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        it = b->graphs.emplace(gk, exec).first;
-    }
-    HIP_TRY(hipGraphLaunch(it->second, s));
-    return NLCH_OK;
+int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
+                            const nlch_sample *samples, int64_t n_samples, int32_t nsteps,
+                            int32_t precision, int32_t algo, void *state, void *scratch,
+                            double *ooi_out, double *energy_out, void *hip_stream) {
+    if (!energy_out) return fail(NLCH_EINVAL, "energy_out must be non-NULL");
+    return solve_impl(models, n_models, samples, n_samples, nsteps, precision, algo, state,
+                      scratch, ooi_out, energy_out, hip_stream);
 }
 
 int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, int64_t y_stride,

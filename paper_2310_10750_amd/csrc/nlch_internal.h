@@ -33,12 +33,15 @@ struct ModelGeo {
 // Per-sample update coefficients: with Lsum the unit-amplitude operator sum
 // sum_{d != 0} e_d (u - u_{+d}),  v = u + (a u - b Lsum),  u' = clamp(v).
 //   a = c1 c_F,  b = c1 h^2 amp,  c1 = tau beta1 / (1 + tau beta1 xi_h).
+// Energy factors: E_h(u) = e_int sum_i u_i Lsum_i + e_pot sum_i (1 - u_i^2)
+//   with e_int = h^4 amp / 2 and e_pot = h^2 c_F / 2.
 struct SampleDesc {
     int64_t offset;   // element offset of the sample's n x n state
     int32_t model;
     int32_t n;
     double a, b;
     float af, bf;
+    double e_int, e_pot;
     int64_t pad;
 };
 
@@ -82,6 +85,21 @@ inline int stream_lanes_cols(int n, int M, int nids) {
     return waves2 < 2048 ? 1 : 2;
 }
 
+// Streaming shape of a group (tuned if the autotuner set one) and the number
+// of workgroups one sample occupies.
+inline void stream_shape(const Group &g, int *R, int *B, int *per_sample) {
+    int r = g.tune_R, b = g.tune_B;
+    if (r != 1 && r != 2) r = stream_lanes_cols(g.n, g.m, g.nids);
+    if (b < 1) b = stream_band_rows(g.n, g.m, 64 * r, g.nids);
+    *R = r;
+    *B = b;
+    *per_sample = ((g.n + 64 * r - 1) / (64 * r)) * ((g.n + b - 1) / b);
+}
+
+// Tile of the direct kernel and the workgroups one sample occupies.
+constexpr int kDirTX = 64, kDirTY = 16;
+inline int direct_tiles(int n) { return ((n + kDirTX - 1) / kDirTX) * ((n + kDirTY - 1) / kDirTY); }
+
 // Kernel variants.
 enum Variant { kDirect = 1, kRowrun = 2, kResident = 3 };
 
@@ -94,14 +112,23 @@ hipError_t launch_count_nonfinite(int prec, const Group &g, const void *src,
 int ooi_chunks(int n);
 hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi,
                       int per_sample_slots, hipStream_t s);
+// Step launches take an optional `epart` (two FP64 energy partial sums per
+// workgroup, workgroups of one sample consecutive); nullptr skips the energy.
 hipError_t launch_direct_step(int prec, bool acc64, const Group &g,
-                              const void *in, void *out, hipStream_t s);
+                              const void *in, void *out, hipStream_t s,
+                              double *epart = nullptr);
 bool rowrun_supported(int prec, bool acc64, int R2, int kernel);
 hipError_t launch_rowrun_step(int prec, bool acc64, const Group &g,
-                              const void *in, void *out, hipStream_t s);
+                              const void *in, void *out, hipStream_t s,
+                              double *epart = nullptr);
 bool resident_supported(int prec, bool acc64, int R2, int kernel, int n);
+// `energy` (nullable): E_h(u^k) of sample s at energy[k * estride + s].
 hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
-                           int nsteps, double *ooi, hipStream_t s);
+                           int nsteps, double *ooi, hipStream_t s,
+                           double *energy = nullptr, int64_t estride = 0);
+// Per sample of the group, the workgroup partials in order -> energy[ids[j]].
+hipError_t launch_energy_final(const Group &g, const double *epart, int per_sample,
+                               double *energy, hipStream_t s);
 hipError_t launch_moments(int K, const double *const *y, const int64_t *m,
                           int64_t stride, double *out, hipStream_t s);
 

@@ -103,6 +103,10 @@ def load():
                                      ctypes.POINTER(nlch_sample), i64, i32, i32,
                                      i32, vp, vp, vp, vp]
     lib.nlch_solve_batch.restype = ctypes.c_int
+    lib.nlch_solve_batch_energy.argtypes = [ctypes.POINTER(nlch_model), i32,
+                                            ctypes.POINTER(nlch_sample), i64, i32, i32,
+                                            i32, vp, vp, vp, vp, vp]
+    lib.nlch_solve_batch_energy.restype = ctypes.c_int
     lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64,
                                   pd, ctypes.POINTER(mfmc_result), vp]
     lib.mfmc_estimate.restype = ctypes.c_int
@@ -204,6 +208,20 @@ def nlch_solve_batch(models, samples, nsteps: int, precision: int, algo: int, st
     _check(load().nlch_solve_batch(models, len(models), samples, len(samples),
                                    int(nsteps), precision, algo, _ptr(state),
                                    _ptr(scratch), _ptr(ooi_out), _stream(stream)))
+
+
+def nlch_solve_batch_energy(models, samples, nsteps: int, precision: int, algo: int,
+                            state, scratch, ooi_out, energy_out, stream=None) -> None:
+    """nlch_solve_batch plus the energy trace: energy_out holds
+    (nsteps + 1) * len(samples) float64, row k = E_h(u^k) per sample."""
+    if not isinstance(models, ctypes.Array):
+        models = (nlch_model * len(models))(*models)
+    if not isinstance(samples, ctypes.Array):
+        samples = (nlch_sample * len(samples))(*samples)
+    _check(load().nlch_solve_batch_energy(models, len(models), samples, len(samples),
+                                          int(nsteps), precision, algo, _ptr(state),
+                                          _ptr(scratch), _ptr(ooi_out), _ptr(energy_out),
+                                          _stream(stream)))
 
 
 def mfmc_estimate(ys, m, alpha=None, stream=None, y_stride=1) -> dict:

@@ -50,6 +50,17 @@ class DeviceBatch:
                               nlch.PRECISIONS[self.prec], algo, self.state,
                               self.scratch, self.ooi, stream)
 
+    def solve_energy(self, algo=nlch.NLCH_ALGO_AUTO, nsteps=None, stream=None):
+        """Solve with the energy trace; returns the (nsteps + 1, n_samples)
+        device array of E_h(u^k)."""
+        import torch
+        k = self.w.nsteps if nsteps is None else nsteps
+        e = torch.full(((k + 1) * len(self.w.samples),), float("nan"), dtype=torch.float64,
+                       device=self.state.device)
+        nlch.nlch_solve_batch_energy(self.models, self.samples, k, nlch.PRECISIONS[self.prec],
+                                     algo, self.state, self.scratch, self.ooi, e, stream)
+        return e.view(k + 1, len(self.w.samples))
+
     def sample_state(self, i):
         n = self.w.models[self.w.samples[i].model].n
         off = self.samples[i].offset

@@ -147,6 +147,12 @@ def test_solve_batch_argument_errors():
     odd = nlch.make_model(64, math.sqrt(7) / 64, 0, 1.0, tau=0.01)
     assert _err(f, [odd], [nlch.nlch_sample(0, 0, 1.0, 1.0, 0)], 5, 1,
                 nlch.NLCH_ALGO_ROWRUN, big, big * 2, big * 3) == nlch.NLCH_EUNSUPPORTED
+    # the energy variant validates the same way, and needs its output
+    fe = nlch.nlch_solve_batch_energy
+    assert _err(fe, [md], S, 5, 1, 0, big, big * 2, big * 3, None) == E
+    assert _err(fe, [md], S, -1, 1, 0, big, big * 2, big * 3, big * 4) == E
+    assert _err(fe, [md], overl, 5, 1, 0, big, big * 2, big * 3, big * 4) == E
+    assert _err(fe, [md], S, 5, 1, nlch.NLCH_ALGO_DIRECT, big, None, big * 3, big * 4) == E
 
 
 def test_mfmc_argument_errors():
