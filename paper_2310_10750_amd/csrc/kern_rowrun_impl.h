@@ -145,8 +145,9 @@ __global__ __launch_bounds__(64) void k_stream(
     constexpr int WIN = 2 * M + R;
     constexpr int CPL = (TW + 63) / 64;  // row-segment elements per lane
     // the ring holds the arithmetic type: a narrow state is widened once per
-    // staged element instead of once per window read
-    __shared__ __align__(16) TA ring[2][TW];
+    // staged element instead of once per window read; rows are padded to
+    // 64 CPL elements so that every lane stores
+    __shared__ __align__(16) TA ring[2][64 * CPL];
 
     const int n = geo->n;
     const int bidx = xcd_remap(blockIdx.x, nblocks);
@@ -159,25 +160,39 @@ __global__ __launch_bounds__(64) void k_stream(
     TS *dst = out + d.offset;
     const int lane = threadIdx.x;
     const int c0 = lane * R;
-    const int rows = (y0 + B <= n ? B : n - y0) + 2 * M;
+    const int bq = y0 + B <= n ? B : n - y0;  // output rows of this band
+    const int rows = bq + 2 * M;
 
+    // wrapped source columns of this lane's staged elements; lanes past the
+    // segment end re-read column 0 into the ring's padding
     int gxs[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         int gx = (x0 - M + lane + 64 * k) % n;
-        gxs[k] = gx + (gx < 0 ? n : 0);
+        gx += gx < 0 ? n : 0;
+        gxs[k] = lane + 64 * k < TW ? gx : 0;
     }
     int gy = (y0 - M) % n;
     gy += gy < 0 ? n : 0;
     TS pre[CPL];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k)
-        if (lane + 64 * k < TW) pre[k] = src[(int64_t)gy * n + gxs[k]];
+    for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
 
     const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
+
+    // Centre values are fetched one row ahead of their use and before that
+    // row's prefetch, so that waiting for them never waits for the prefetch.
+    int xcl[R];
+    TS cnext[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int x = x0 + c0 + c;
+        xcl[c] = x < n ? x : 0;
+        cnext[c] = src[(int64_t)y0 * n + xcl[c]];
+    }
 
     TA acc[P][R];
 #pragma unroll
@@ -196,26 +211,29 @@ __global__ __launch_bounds__(64) void k_stream(
             if (p < rows) {
                 // stage row p, prefetch row p + 1
                 TA *slot = ring[i & 1 ? (pb & 1) ^ 1 : (pb & 1)];
-#pragma unroll
-                for (int k = 0; k < CPL; ++k)
-                    if (lane + 64 * k < TW) slot[lane + 64 * k] = to_acc<TA>(pre[k]);
-                gy = gy + 1 < n ? gy + 1 : 0;
-                if (p + 1 < rows) {
-#pragma unroll
-                    for (int k = 0; k < CPL; ++k)
-                        if (lane + 64 * k < TW) pre[k] = src[(int64_t)gy * n + gxs[k]];
-                }
-                // centre values of the output finishing at this row
+                // centre values of the output finishing at this row (fetched
+                // at the previous row), then those of the next row's output
+                // (row index clamped into the band: always a valid address)
                 const int q = p - 2 * M;
                 const int y = y0 + q;
                 TS cen[R];
-                if (q >= 0) {
 #pragma unroll
-                    for (int c = 0; c < R; ++c) {
-                        const int x = x0 + c0 + c;
-                        cen[c] = src[(int64_t)y * n + (x < n ? x : 0)];
-                    }
+                for (int c = 0; c < R; ++c) cen[c] = cnext[c];
+                {
+                    int qn = q + 1;
+                    qn = qn < 0 ? 0 : (qn < bq ? qn : bq - 1);
+#pragma unroll
+                    for (int c = 0; c < R; ++c)
+                        cnext[c] = src[(int64_t)(y0 + qn) * n + xcl[c]];
                 }
+#pragma unroll
+                for (int k = 0; k < CPL; ++k)
+                    slot[lane + 64 * k] = to_acc<TA>(pre[k]);
+                gy = gy + 1 < n ? gy + 1 : 0;
+                // unconditional (one row past the band at the end; the row
+                // index wraps, so the address stays inside the sample)
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
                 __syncthreads();  // one wave: makes the staged row visible
                 TA win[WIN];
                 load_window<WIN, (R % 2 == 0)>(slot + c0, win);
