@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--algo", type=int, default=0x800,
+    ap.add_argument("--algo", type=lambda v: int(v, 0), default=0x800,
                     help="nlch algorithm word (default AUTO | AUTOTUNE)")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--fp64-samples", type=int, default=4)

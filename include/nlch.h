@@ -75,10 +75,16 @@ extern "C" {
                                         synchronises hip_stream                 */
 #define NLCH_ALGO_AUTOTUNE 0x800 /* on the first call of a batch, time the
                                     streaming kernel's launch shapes (lanes'
-                                    columns, band height) on the caller's
-                                    buffers (reads state, writes scratch),
-                                    keep the fastest; synchronises hip_stream.
-                                    Results do not depend on the shape.       */
+                                    columns, band height, waves per band) on
+                                    the caller's buffers (reads state, writes
+                                    scratch), keep the fastest (cached per
+                                    process); synchronises hip_stream.  Shapes
+                                    that split a band over several waves sum
+                                    the outputs next to the split points in
+                                    two parts: results can differ from the
+                                    default shape by rounding only.  Without
+                                    this flag the shape is a fixed function
+                                    of the batch, so results repeat exactly. */
 
 /* One fidelity level ("model"): lattice, horizon, kernel and evolution
  * parameters (Sec. 2.1 and Sec. 4). */
@@ -183,6 +189,18 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
                             int32_t nsteps, int32_t precision, int32_t algo,
                             void *state, void *scratch, double *ooi_out,
                             double *energy_out, void *hip_stream);
+
+/* Manual launch shape of the streaming (ROWRUN) kernel for later
+ * nlch_solve_batch calls in this process, overriding the default shape and
+ * NLCH_ALGO_AUTOTUNE: R columns per lane (1 or 2), W waves per band (1, 2,
+ * 4 or 8), each of the first W-1 waves walking `periods` ring periods of
+ * 2m+1 rows (W > 1), and band height B (W = 1); 0 keeps the default of a
+ * field, and (0, 0, 0, 0) restores the default shape.  W > 1 applies to
+ * groups with FP32 arithmetic and m <= 16 (others use W = 1); a group whose
+ * partial-sum areas for W waves would not fit in LDS uses fewer waves.
+ * Results change with W > 1 by rounding only (see NLCH_ALGO_AUTOTUNE).
+ * Host only; returns NLCH_EINVAL for values outside those ranges. */
+int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
 
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
  * y_dev[j]: device pointer to the outputs of model j+1, the output for

@@ -202,22 +202,36 @@ static void step_all(const orc_op *op, double tb, double denom, const double *u,
     }
 }
 
-/* Discrete energy E_h(u), definition in the header. */
+/* Kahan-compensated accumulation: the energy sums n^2 N positive terms, and
+ * a plain running sum would carry ~sqrt(n^2 N) eps of its own rounding. */
+static void kahan_add(double *sum, double *comp, double v)
+{
+    double y = v - *comp;
+    double t = *sum + y;
+    *comp = (t - *sum) - y;
+    *sum = t;
+}
+
+/* Discrete energy E_h(u), definition in the header.  Per site the N
+ * interaction terms are summed in canonical order; the per-site sums and the
+ * potential terms are accumulated with compensation. */
 static double energy(const orc_op *op, double c_F, const double *u)
 {
     int n = op->n;
     double h2 = 1.0 / ((double)n * n);
-    double inter = 0.0, pot = 0.0;
+    double inter = 0.0, inter_c = 0.0, pot = 0.0, pot_c = 0.0;
     for (int y = 0; y < n; y++)
         for (int x = 0; x < n; x++) {
             double ui = u[(int64_t)y * n + x];
+            double site = 0.0;
             for (int k = 0; k < op->N; k++) {
                 int yy = wrap(y + op->ddy[k], n);
                 int xx = wrap(x + op->ddx[k], n);
                 double d = ui - u[(int64_t)yy * n + xx];
-                inter += op->wd[k] * d * d;
+                site += op->wd[k] * d * d;
             }
-            pot += 1.0 - ui * ui;
+            kahan_add(&inter, &inter_c, site);
+            kahan_add(&pot, &pot_c, 1.0 - ui * ui);
         }
     return h2 * (0.25 * inter + 0.5 * c_F * pot);
 }

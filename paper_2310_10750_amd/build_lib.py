@@ -44,18 +44,31 @@ def _compile(src):
     return src, obj, r.returncode, r.stdout + r.stderr, time.time() - t0
 
 
-def build(verbose: bool = True, jobs: int = None) -> str:
+def _stale(src):
+    """True unless the unit's object is newer than it and every header."""
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [
+        os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + [
+        os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(f) for f in deps) > os.path.getmtime(obj)
+
+
+def build(verbose: bool = True, jobs: int = None, incremental: bool = False) -> str:
+    """Compiles every unit (or, with incremental, only those whose object is
+    older than its sources) and links the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 4)))
-    objs = []
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
+    jobs = jobs or min(max(1, len(todo)), max(1, min(16, os.cpu_count() or 4)))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in srcs]
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for src, obj, rc, log, dt in ex.map(_compile, srcs):
+        for src, obj, rc, log, dt in ex.map(_compile, todo):
             if verbose:
                 print("  hipcc %-28s %6.1fs" % (src, dt), flush=True)
             if rc != 0:
                 raise RuntimeError("hipcc failed on %s:\n%s" % (src, log))
-            objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -67,6 +80,6 @@ def build(verbose: bool = True, jobs: int = None) -> str:
 
 if __name__ == "__main__":
     t = time.time()
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))
     print("built in %.1fs" % (time.time() - t))
     sys.exit(0)

@@ -13,34 +13,55 @@ namespace nlch {
 
 constexpr size_t kLdsBytes = 160 * 1024;
 
-// Streaming shape: lanes own R columns of a 64R-column strip (R = 2 halves
-// the window reads per site, R = 1 halves the register ring), and a wave's
-// band height B trades parallelism against the 2m-row window overhead of
-// each band.  The heuristic below aims at about 12 waves per CU with bands
-// of at least max(16, 2m) rows; the host's autotuner may override (R, B).
-// Every shape gives bit-identical results: each site sums the same window
-// sums in the same row order.
+// Streaming shape (see stream_shape): lanes own R columns of a 64R-column
+// strip (R = 2 halves the window reads per site, R = 1 halves the register
+// ring); a band of B output rows is walked by W waves.  One wave per band
+// (k_stream) repeats the 2m halo rows of every band; W > 1 waves (k_band,
+// built for FP32 and m <= 16) share a band and hand partial sums over in LDS
+// instead.  Shapes with W = 1 give bit-identical results for every (R, B):
+// each site sums the same window sums in the same row order; with W > 1 the
+// sums of the outputs next to a hand-over point are formed in two parts,
+// which changes their rounding only.
 template <int R2, int R, class TS, class TA, bool GAUSS>
-hipError_t stream_launch(const Group &g, int B, const void *in, void *out, hipStream_t s,
-                         double *epart) {
+hipError_t stream_launch(const Group &g, const StreamShape &sh, const void *in, void *out,
+                         hipStream_t s, double *epart) {
     constexpr int TX = 64 * R;
+    constexpr int P = Disc<R2>::P;
     const int strips = (g.n + TX - 1) / TX;
-    const int bands = (g.n + B - 1) / B;
+    const int bands = (g.n + sh.B - 1) / sh.B;
     const int64_t nb = (int64_t)strips * bands * g.nids;
-    if (nb > 0x7fffffff || B < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
-                       g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, B, strips, bands,
-                       (int)nb, epart);
-    return hipGetLastError();
+    if (nb > 0x7fffffff || sh.B < 1 || sh.W < 1 || sh.W > 8) return hipErrorInvalidValue;
+    if (sh.W == 1) {
+        hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
+                           g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, sh.B, strips, bands,
+                           (int)nb, epart);
+        return hipGetLastError();
+    }
+    if constexpr (band_built(Disc<R2>::M, (int)sizeof(TA))) {
+        const size_t lds = StreamLds<R2, R, TA>::bytes(sh.W);
+        if (lds > kLdsBytes - 1024 ||
+            lds != stream_lds_bytes(R, Disc<R2>::M, sh.W, (int)sizeof(TA)) ||
+            sh.L % P != 0 || sh.L < P)
+            return hipErrorInvalidValue;
+        auto f = k_band<R2, R, TS, TA, GAUSS>;
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kLdsBytes - 1024)) != hipSuccess)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(f, dim3((unsigned)nb), dim3(64 * sh.W), lds, s, g.sd, g.ids, g.geo,
+                           (const TS *)in, (TS *)out, sh.B, sh.L, strips, bands, (int)nb,
+                           epart);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t s,
                          double *epart) {
-    int R = 1, B = 1, per_sample = 0;
-    stream_shape(g, &R, &B, &per_sample);
-    if (R == 1) return stream_launch<R2, 1, TS, TA, GAUSS>(g, B, in, out, s, epart);
-    return stream_launch<R2, 2, TS, TA, GAUSS>(g, B, in, out, s, epart);
+    const StreamShape sh = stream_shape(g);
+    if (sh.R == 1) return stream_launch<R2, 1, TS, TA, GAUSS>(g, sh, in, out, s, epart);
+    return stream_launch<R2, 2, TS, TA, GAUSS>(g, sh, in, out, s, epart);
 }
 
 // Resident layout: one wave per band of kResB rows, lanes own one (n = 64)

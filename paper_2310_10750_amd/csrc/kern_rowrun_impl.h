@@ -280,6 +280,247 @@ __global__ __launch_bounds__(64) void k_stream(
 }
 
 // ---------------------------------------------------------------------------
+// Shared-band streaming step (W >= 2 waves per workgroup).  The workgroup
+// owns a strip of 64R columns and a band of BW output rows and walks the
+// band's BW + 2m input rows once, split into consecutive runs, one per wave;
+// each wave walks its run as k_stream does.  The runs meet inside the band:
+// the first 2m outputs a wave retires (missing the rows of the wave above)
+// go to LDS, and after one barrier the wave above adds them to its last 2m
+// pending outputs and finishes those.  Every wave but the last walks exactly
+// L rows, a multiple of the ring period, so that its pending outputs sit in
+// known registers at the end; the last walks the rest (at least 2m rows).
+// Compared with one wave per band, the 2m halo rows are walked once per
+// band of W runs instead of once per run.
+// ---------------------------------------------------------------------------
+
+// LDS layout of k_band (arithmetic type TA): per wave a two-row staging
+// ring and 2m rows of 64R partial sums.
+template <int R2, int R, class TA>
+struct StreamLds {
+    static constexpr int M = Disc<R2>::M;
+    static constexpr int TW = 64 * R + 2 * M;
+    static constexpr int CPL = (TW + 63) / 64;  // row-segment elements per lane
+    static constexpr int RING = 2 * 64 * CPL;   // ring elements per wave
+    static constexpr int HEAD = 2 * M * 64 * R;  // partial-sum elements per wave
+    static constexpr size_t bytes(int W) { return (size_t)W * (RING + HEAD) * sizeof(TA); }
+    static_assert(RING == 2 * 64 * ((64 * R + 2 * M + 63) / 64), "see stream_lds_bytes");
+};
+
+template <int R2, int R, class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(512) void k_band(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const TS *__restrict__ in,
+    TS *__restrict__ out, int BW, int L, int strips, int bands, int nblocks,
+    double *__restrict__ epart) {
+    using LD = StreamLds<R2, R, TA>;
+    constexpr int M = Disc<R2>::M, P = Disc<R2>::P;
+    constexpr int TX = 64 * R;
+    constexpr int TW = LD::TW;
+    constexpr int WIN = 2 * M + R;
+    constexpr int CPL = LD::CPL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+
+    const int W = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // the ring holds the arithmetic type: a narrow state is widened once per
+    // staged element instead of once per window read; rows are padded to
+    // 64 CPL elements so that every lane stores
+    TA *ring = reinterpret_cast<TA *>(smem_raw) + (size_t)wv * LD::RING;
+    TA *heads = reinterpret_cast<TA *>(smem_raw) + (size_t)W * LD::RING;
+
+    const int n = geo->n;
+    const int bidx = xcd_remap(blockIdx.x, nblocks);
+    const int per_sample = strips * bands;
+    const SampleDesc d = sd[ids[bidx / per_sample]];
+    const int tile = bidx % per_sample;
+    const int x0 = (tile % strips) * TX;
+    const int y0 = (tile / strips) * BW;
+    const TS *src = in + d.offset;
+    TS *dst = out + d.offset;
+    const int c0 = lane * R;
+    const int bq = y0 + BW <= n ? BW : n - y0;  // output rows of this band
+    const int T = bq + 2 * M;                    // input rows of this band
+    // waves with rows to walk; wave wv walks input rows [s, s + Lw) of the
+    // band's T rows and retires outputs q = s + t - 2m (q relative to y0)
+    const int weff = bq / L + 1 < W ? bq / L + 1 : W;
+    const int s = wv * L;
+    const int Lw = wv < weff - 1 ? L : T - s;
+
+    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    TA g[M + 1];
+#pragma unroll
+    for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
+
+    int xcl[R];  // centre columns (clamped in range for idle lanes)
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int x = x0 + c0 + c;
+        xcl[c] = x < n ? x : 0;
+    }
+
+    TA acc[P][R];
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[i][c] = TA(-0.0);
+    // energy partial sums of the input state (only with epart): sum u Lsum
+    // and sum (1 - u^2) over this lane's outputs in the arithmetic type, then
+    // across the workgroup in FP64
+    TA e_ul = TA(0), e_pot = TA(0);
+
+    if (wv < weff) {
+        // wrapped source columns of this lane's staged elements; lanes past
+        // the segment end re-read column 0 into the ring's padding
+        int gxs[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            int gx = (x0 - M + lane + 64 * k) % n;
+            gx += gx < 0 ? n : 0;
+            gxs[k] = lane + 64 * k < TW ? gx : 0;
+        }
+        int gy = (y0 - M + s) % n;
+        gy += gy < 0 ? n : 0;
+        TS pre[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+        // Centre values are fetched one row ahead of their use, so that the
+        // wait before staging a row covers exactly the previous row's loads.
+        TS cnext[R];
+        {
+            int q0 = s - 2 * M;
+            q0 = q0 < 0 ? 0 : (q0 < bq ? q0 : bq - 1);
+#pragma unroll
+            for (int c = 0; c < R; ++c) cnext[c] = src[(int64_t)(y0 + q0) * n + xcl[c]];
+        }
+
+        for (int pb = 0; pb < Lw; pb += P) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int t = pb + i;
+                if (t < Lw) {
+                    TA *slot = ring + (i & 1 ? (pb & 1) ^ 1 : (pb & 1)) * (64 * CPL);
+                    // centre values of the output retiring at this row, then
+                    // those of the next (row clamped into the band)
+                    const int q = s + t - 2 * M;
+                    TS cen[R];
+#pragma unroll
+                    for (int c = 0; c < R; ++c) cen[c] = cnext[c];
+                    {
+                        int qn = q + 1;
+                        qn = qn < 0 ? 0 : (qn < bq ? qn : bq - 1);
+#pragma unroll
+                        for (int c = 0; c < R; ++c)
+                            cnext[c] = src[(int64_t)(y0 + qn) * n + xcl[c]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) slot[lane + 64 * k] = to_acc<TA>(pre[k]);
+                    gy = gy + 1 < n ? gy + 1 : 0;
+                    // unconditional (one row past the run at the end; the row
+                    // index wraps, so the address stays inside the sample)
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+                    // the ring is private to the wave and LDS operations of
+                    // one wave complete in order: only keep the compiler from
+                    // reordering the staging stores and the window loads
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    TA win[WIN];
+                    load_window<WIN, (R % 2 == 0)>(slot + c0, win);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        // input row t feeds output t - m - dy (walk-relative),
+                        // ring slot (t - m - dy) mod P
+                        row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
+                            acc[((i - M - dy) % P + P) % P][c] += v;
+                        });
+                    }
+                    const int done = (i + 1) % P;
+                    if (t >= 2 * M) {
+                        // complete: every input row of this output is in the run
+                        const int y = y0 + q;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) {
+                            const int x = x0 + c0 + c;
+                            const TA u = to_acc<TA>(cen[c]);
+                            const TA lsum = ce * u - acc[done][c];
+                            if (x < n) {
+                                dst[(int64_t)y * n + x] =
+                                    to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                                if (epart) {
+                                    e_ul += u * lsum;
+                                    e_pot += TA(1) - u * u;
+                                }
+                            }
+                        }
+                    } else if (wv > 0) {
+                        // partial (rows of the wave above missing): hand over
+#pragma unroll
+                        for (int c = 0; c < R; ++c)
+                            heads[((size_t)wv * 2 * M + t) * TX + c0 + c] = acc[done][c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[done][c] = TA(-0.0);
+                }
+            }
+        }
+    }
+
+    {
+        __syncthreads();
+        if (wv < weff - 1) {
+            // Last 2m pending outputs q = s + L - 2m + k: ring slot (k + 1)
+            // mod P (L is a multiple of P), plus the next wave's first 2m.
+#pragma unroll
+            for (int k = 0; k < 2 * M; ++k) {
+                const int y = y0 + s + L - 2 * M + k;
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const int x = x0 + c0 + c;
+                    const TA sum = acc[(k + 1) % P][c] +
+                                   heads[((size_t)(wv + 1) * 2 * M + k) * TX + c0 + c];
+                    const TA u = to_acc<TA>(src[(int64_t)y * n + xcl[c]]);
+                    const TA lsum = ce * u - sum;
+                    if (x < n) {
+                        dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                        if (epart) {
+                            e_ul += u * lsum;
+                            e_pot += TA(1) - u * u;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (epart) {
+        // fixed shuffle tree, then the waves in order: the partials do not
+        // depend on timing
+        double s_ul = (double)e_ul, s_pot = (double)e_pot;
+        for (int o = 32; o > 0; o >>= 1) {
+            s_ul += __shfl_xor(s_ul, o, 64);
+            s_pot += __shfl_xor(s_pot, o, 64);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            red[2 * wv] = s_ul;
+            red[2 * wv + 1] = s_pot;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int w = 0; w < W; ++w) {
+                a0 += red[2 * w];
+                a1 += red[2 * w + 1];
+            }
+            epart[2 * (int64_t)bidx] = a0;
+            epart[2 * (int64_t)bidx + 1] = a1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS-resident multi-step kernel: one workgroup holds one whole n x n sample
 // in LDS (rows padded with an m-column periodic halo) and runs every step
 // without touching HBM.  Wave b owns the band of B rows starting at b*B

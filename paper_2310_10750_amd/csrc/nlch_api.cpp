@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -232,8 +233,15 @@ struct Batch {
     }
 };
 
+// Streams the launch groups of one solve run on: the caller's stream and
+// up to kAuxStreams more (default priority), forked and joined with events.
+constexpr int kAuxStreams = 3;
+
 struct DevCtx {
     hipStream_t capture = nullptr;
+    hipStream_t aux[kAuxStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kAuxStreams] = {};
     unsigned int *counter = nullptr;   // non-finite counter (device)
     unsigned int *counter_h = nullptr; // pinned host copy
     double *mom = nullptr;             // moments (device)
@@ -251,6 +259,11 @@ int dev_ctx(DevCtx **out) {
     DevCtx &c = g_dev[dev];
     if (!c.capture) {
         HIP_TRY(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+        for (int i = 0; i < kAuxStreams; ++i) {
+            HIP_TRY(hipStreamCreateWithFlags(&c.aux[i], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
         HIP_TRY(hipMalloc((void **)&c.counter, sizeof(unsigned int)));
         HIP_TRY(hipHostMalloc((void **)&c.counter_h, sizeof(unsigned int), hipHostMallocDefault));
         HIP_TRY(hipMalloc((void **)&c.mom, sizeof(double) * 8 * NLCH_MFMC_MAX_K));
@@ -398,6 +411,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         g.R2 = (int32_t)mi[i].R2;
         g.kernel = models[i].kernel;
         g.model = i;
+        g.ta_bytes = prec == kF64 ? 8 : 4;
         id_off.push_back(ids.size());
         ids.insert(ids.end(), per_model[i].begin(), per_model[i].end());
         b->groups.push_back(g);
@@ -439,7 +453,11 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
 }
 
 // Autotuner of the streaming launch shape, cached per (device, precision,
-// disc, kernel, lattice, group size).
+// disc, kernel, lattice, group size).  Candidates, for R = 1 and R = 2
+// columns per lane: one wave per band with band heights
+// max(16, 2m) 2^k, and (shared-band kernels: FP32, m <= 16) W = 2, 4, 8
+// waves per band walking L = k (2m+1) rows each (k = 1, 2, 4).  Every
+// candidate is timed over three launches after a warm-up.
 struct TuneKey {
     int dev, prec, R2, kernel, n, nids;
     bool operator<(const TuneKey &o) const {
@@ -447,38 +465,57 @@ struct TuneKey {
                std::tie(o.dev, o.prec, o.R2, o.kernel, o.n, o.nids);
     }
 };
-std::map<TuneKey, std::pair<int, int>> g_tuned;
+struct TuneVal {
+    int R, B, W, L;
+};
+std::map<TuneKey, TuneVal> g_tuned;
+TuneVal g_force{0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods)
+
+void set_shape(Group &g, const TuneVal &v) {
+    g.tune_R = v.R;
+    g.tune_B = v.B;
+    g.tune_W = v.W;
+    g.tune_L = v.L;
+}
 
 int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void *out,
                    hipStream_t s) {
     const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.nids};
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-        g.tune_R = it->second.first;
-        g.tune_B = it->second.second;
+        set_shape(g, it->second);
         return NLCH_OK;
     }
+    const int P = 2 * g.m + 1;
     const int bmin = g.m * 2 > 16 ? g.m * 2 : 16;
-    std::vector<std::pair<int, int>> cands;
+    std::vector<TuneVal> cands;
     for (int R = 1; R <= 2; ++R) {
         const int strips = (g.n + 64 * R - 1) / (64 * R);
         for (int B = bmin;; B *= 2) {
             const int Bc = B < g.n ? B : g.n;
             const int64_t waves = (int64_t)strips * ((g.n + Bc - 1) / Bc) * g.nids;
-            if (waves >= 128 || Bc == bmin || Bc == g.n) cands.push_back({R, Bc});
+            if (waves >= 128 || Bc == bmin || Bc == g.n) cands.push_back({R, Bc, 1, 0});
             if (Bc >= g.n) break;
         }
+        for (int W = 2; W <= 8 && band_built(g.m, g.ta_bytes); W *= 2)
+            for (int k = 1; k <= 4; k *= 2) {
+                const int L = k * P;
+                if (W * L - 2 * g.m > 2 * g.n) continue;  // far more rows than the lattice
+                cands.push_back({R, 0, W, L});
+            }
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    std::pair<int, int> pick{0, 0};
-    for (auto c : cands) {
-        g.tune_R = c.first;
-        g.tune_B = c.second;
+    TuneVal pick{0, 0, 0, 0};
+    for (const TuneVal &c : cands) {
+        set_shape(g, c);
         hipError_t e = launch_rowrun_step(prec, acc64, g, in, out, s);  // warm-up
-        if (e != hipSuccess) continue;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
         HIP_TRY(hipEventRecord(e0, s));
         for (int r = 0; r < 3; ++r) HIP_TRY(launch_rowrun_step(prec, acc64, g, in, out, s));
         HIP_TRY(hipEventRecord(e1, s));
@@ -492,9 +529,12 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g.tune_R = pick.first;
-    g.tune_B = pick.second;
+    set_shape(g, pick);
     g_tuned[key] = pick;
+    if (std::getenv("NLCH_VERBOSE"))
+        std::fprintf(stderr, "nlch autotune: n=%d R2=%d samples=%d -> R=%d W=%d L=%d B=%d "
+                     "(%.3f ms per launch)\n", g.n, g.R2, g.nids, pick.R, pick.W, pick.L,
+                     stream_shape(g).B, best / 3.0f);
     return NLCH_OK;
 }
 
@@ -506,11 +546,7 @@ hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const 
 
 // Workgroups one sample of a streaming group occupies per step launch.
 int step_blocks_per_sample(int variant, const Group &g) {
-    if (variant == kRowrun) {
-        int R = 1, B = 1, ps = 0;
-        stream_shape(g, &R, &B, &ps);
-        return ps;
-    }
+    if (variant == kRowrun) return stream_shape(g).per_sample;
     return direct_tiles(g.n);
 }
 
@@ -543,51 +579,66 @@ int ensure_epart(Batch &b) {
     return NLCH_OK;
 }
 
-// Enqueues a whole batch solve on stream s.  With `energy` (n_samples-strided
-// rows k = 0..nsteps), every step launch also reduces E_h of its input state,
-// and one more launch per streaming group evaluates E_h(u^nsteps) (its update
-// goes to `scratch` and is dropped).
-int enqueue_solve(Batch &b, int prec, bool acc64, int nsteps, void *state, void *scratch,
-                  double *ooi, double *energy, int64_t estride, hipStream_t s) {
-    bool any_stream = false;
-    for (size_t gi = 0; gi < b.groups.size(); ++gi) {
-        const Group &g = b.groups[gi];
-        if (b.variant[gi] == kResident) {
-            HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, s, energy, estride));
-        } else {
-            any_stream = true;
-        }
+// Enqueues one launch group's whole solve on stream s.  With `energy`
+// (n_samples-strided rows k = 0..nsteps), every step launch also reduces E_h
+// of its input state, and one more launch evaluates E_h(u^nsteps) (its
+// update goes to `scratch` and is dropped).  Streaming groups ping-pong
+// between state and scratch, projecting into whichever buffer makes the last
+// step land in `state`; every group touches only its own samples' elements.
+int enqueue_group(Batch &b, size_t gi, int prec, bool acc64, int nsteps, void *state,
+                  void *scratch, double *ooi, double *energy, int64_t estride,
+                  hipStream_t s) {
+    const Group &g = b.groups[gi];
+    const int variant = b.variant[gi];
+    if (variant == kResident) {
+        HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, s, energy, estride));
+        return NLCH_OK;
     }
-    if (!any_stream) return NLCH_OK;
-    // Ping-pong: project into buf0 so that the last step lands in `state`.
     void *buf0 = (nsteps % 2) ? scratch : state;
     void *buf1 = (buf0 == state) ? scratch : state;
-    for (size_t gi = 0; gi < b.groups.size(); ++gi)
-        if (b.variant[gi] != kResident) HIP_TRY(launch_project(prec, b.groups[gi], state, buf0, s));
-    auto step_all = [&](int k, const void *in, void *out) -> int {
-        for (size_t gi = 0; gi < b.groups.size(); ++gi) {
-            if (b.variant[gi] == kResident) continue;
-            const Group &g = b.groups[gi];
-            double *ep = energy ? group_epart(b, gi) : nullptr;
-            HIP_TRY(launch_step(b.variant[gi], prec, acc64, g, in, out, s, ep));
-            if (energy)
-                HIP_TRY(launch_energy_final(g, ep, step_blocks_per_sample(b.variant[gi], g),
-                                            energy + (int64_t)k * estride, s));
-        }
-        return NLCH_OK;
-    };
+    HIP_TRY(launch_project(prec, g, state, buf0, s));
+    double *ep = energy ? group_epart(b, gi) : nullptr;
+    const int ps = step_blocks_per_sample(variant, g);
     void *cur = buf0, *nxt = buf1;
-    for (int k = 0; k < nsteps; ++k) {
-        int rc = step_all(k, cur, nxt);
-        if (rc) return rc;
+    for (int k = 0; k <= nsteps; ++k) {
+        if (k == nsteps) {
+            if (!energy) break;
+            cur = state;
+            nxt = scratch;
+        }
+        HIP_TRY(launch_step(variant, prec, acc64, g, cur, nxt, s, ep));
+        if (energy) HIP_TRY(launch_energy_final(g, ep, ps, energy + (int64_t)k * estride, s));
         std::swap(cur, nxt);
     }
-    if (energy) {
-        int rc = step_all(nsteps, state, scratch);
+    HIP_TRY(launch_ooi(prec, g, state, ooi, 2, s));
+    return NLCH_OK;
+}
+
+// Enqueues a whole batch solve on stream s.  The launch groups are
+// independent, so with several groups each runs on its own stream (the
+// caller's and the context's auxiliary streams, forked from and joined back
+// into s with events): a long lattice's step chain overlaps the other
+// levels' launches.
+int enqueue_solve(Batch &b, DevCtx &ctx, int prec, bool acc64, int nsteps, void *state,
+                  void *scratch, double *ooi, double *energy, int64_t estride, hipStream_t s) {
+    const size_t G = b.groups.size();
+    if (G == 1)
+        return enqueue_group(b, 0, prec, acc64, nsteps, state, scratch, ooi, energy, estride, s);
+    const int naux = (int)std::min<size_t>(G - 1, (size_t)kAuxStreams);
+    HIP_TRY(hipEventRecord(ctx.fork, s));
+    for (int i = 0; i < naux; ++i) HIP_TRY(hipStreamWaitEvent(ctx.aux[i], ctx.fork, 0));
+    // group 0 (the first model, the high-fidelity level in an MFMC batch) on
+    // the caller's stream, the rest round-robin on the auxiliary streams
+    for (size_t gi = 0; gi < G; ++gi) {
+        hipStream_t sg = gi == 0 ? s : ctx.aux[(gi - 1) % naux];
+        int rc = enqueue_group(b, gi, prec, acc64, nsteps, state, scratch, ooi, energy,
+                               estride, sg);
         if (rc) return rc;
     }
-    for (size_t gi = 0; gi < b.groups.size(); ++gi)
-        if (b.variant[gi] != kResident) HIP_TRY(launch_ooi(prec, b.groups[gi], state, ooi, 2, s));
+    for (int i = 0; i < naux; ++i) {
+        HIP_TRY(hipEventRecord(ctx.join[i], ctx.aux[i]));
+        HIP_TRY(hipStreamWaitEvent(s, ctx.join[i], 0));
+    }
     return NLCH_OK;
 }
 
@@ -683,13 +734,24 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
             return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
     }
 
-    if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
+    if (g_force.R || g_force.W || g_force.L || g_force.B) {
+        // shape set by nlch_set_stream_shape (k periods per wave -> rows)
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            if (b->variant[gi] != kRowrun) continue;
+            Group &g = b->groups[gi];
+            const int k = g_force.L > 0 ? g_force.L : 1;
+            set_shape(g, {g_force.R, g_force.B, g_force.W, k * (2 * g.m + 1)});
+        }
+        b->tuned = false;
+    } else if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
             if (b->variant[gi] != kRowrun) continue;
             rc = autotune_group(b->groups[gi], b->device, precision, acc64, state, scratch, s);
             if (rc) return rc;
         }
         b->tuned = true;
+    } else if (!(algo & NLCH_ALGO_AUTOTUNE)) {
+        for (Group &g : b->groups) set_shape(g, {0, 0, 0, 0});
     }
 
     if (energy_out) {
@@ -698,8 +760,8 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     }
 
     if (algo & NLCH_ALGO_NOGRAPH)
-        return enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, energy_out,
-                             n_samples, s);
+        return enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
+                             energy_out, n_samples, s);
 
     std::vector<uint8_t> gk;
     append_bytes(gk, state);
@@ -707,11 +769,17 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     append_bytes(gk, ooi_out);
     append_bytes(gk, energy_out);
     append_bytes(gk, nsteps);
+    for (const Group &g : b->groups) {
+        append_bytes(gk, g.tune_R);
+        append_bytes(gk, g.tune_B);
+        append_bytes(gk, g.tune_W);
+        append_bytes(gk, g.tune_L);
+    }
     auto it = b->graphs.find(gk);
     if (it == b->graphs.end()) {
         HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
-        rc = enqueue_solve(*b, precision, acc64, nsteps, state, scratch, ooi_out, energy_out,
-                           n_samples, ctx->capture);
+        rc = enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
+                           energy_out, n_samples, ctx->capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
         if (rc) {
@@ -827,6 +895,16 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     const Group &g = b->groups[0];
     HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
     if (ooi_out) HIP_TRY(launch_ooi(precision, g, u_out, ooi_out, 2, s));
+    return NLCH_OK;
+}
+
+int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
+    if (R < 0 || R > 2 || !(W == 0 || W == 1 || W == 2 || W == 4 || W == 8) || periods < 0 ||
+        periods > 64 || B < 0)
+        return fail(NLCH_EINVAL, "bad streaming shape (R in 0..2, W in {0,1,2,4,8}, "
+                                 "periods 0..64, B >= 0)");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force = {R, B, W, periods};
     return NLCH_OK;
 }
 

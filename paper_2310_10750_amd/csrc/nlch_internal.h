@@ -57,7 +57,9 @@ struct Group {
     int32_t n, m, R2;
     int32_t kernel;
     int32_t model;
-    int32_t tune_R, tune_B;  // streaming shape (0 = heuristic)
+    int32_t tune_R, tune_B;  // streaming shape (0 = heuristic): columns per
+    int32_t tune_W, tune_L;  //   lane, band rows, waves per band, rows per wave
+    int32_t ta_bytes;        // size of the arithmetic type (4 or 8)
 };
 
 // Heuristic streaming shape of the row-run kernel: lanes own R columns of a
@@ -85,15 +87,41 @@ inline int stream_lanes_cols(int n, int M, int nids) {
     return waves2 < 2048 ? 1 : 2;
 }
 
-// Streaming shape of a group (tuned if the autotuner set one) and the number
-// of workgroups one sample occupies.
-inline void stream_shape(const Group &g, int *R, int *B, int *per_sample) {
-    int r = g.tune_R, b = g.tune_B;
-    if (r != 1 && r != 2) r = stream_lanes_cols(g.n, g.m, g.nids);
-    if (b < 1) b = stream_band_rows(g.n, g.m, 64 * r, g.nids);
-    *R = r;
-    *B = b;
-    *per_sample = ((g.n + 64 * r - 1) / (64 * r)) * ((g.n + b - 1) / b);
+// Launch shape of the streaming kernel: R columns per lane, W waves per
+// workgroup, band of B output rows; with W > 1 every wave but the last walks
+// L rows (a multiple of the ring period 2m+1) and B = W L - 2m.
+struct StreamShape {
+    int R, W, L, B, per_sample;
+};
+
+// LDS bytes of the streaming kernel: per wave a two-row staging ring of
+// 64 ceil((64R + 2m)/64) elements, and for W > 1 2m x 64R partial sums.
+inline size_t stream_lds_bytes(int R, int M, int W, int ta_bytes) {
+    const size_t ring = 2 * 64 * (size_t)((64 * R + 2 * M + 63) / 64);
+    const size_t head = W > 1 ? (size_t)2 * M * 64 * R : 0;
+    return (size_t)W * (ring + head) * ta_bytes;
+}
+
+// Shared-band kernels are built for FP32 arithmetic and horizons m <= 16 (for
+// wider discs the 2m rows of partial sums per wave limit occupancy too much).
+constexpr bool band_built(int M, int ta_bytes) { return ta_bytes == 4 && M <= 16; }
+
+inline StreamShape stream_shape(const Group &g) {
+    StreamShape sh;
+    sh.R = (g.tune_R == 1 || g.tune_R == 2) ? g.tune_R : stream_lanes_cols(g.n, g.m, g.nids);
+    sh.W = g.tune_W > 1 && band_built(g.m, g.ta_bytes) ? g.tune_W : 1;
+    // fewer waves per band where the partial-sum areas would not fit in LDS
+    while (sh.W > 1 && stream_lds_bytes(sh.R, g.m, sh.W, g.ta_bytes) > 159 * 1024) sh.W /= 2;
+    if (sh.W > 1) {
+        sh.L = g.tune_L;
+        sh.B = sh.W * sh.L - 2 * g.m;
+    } else {
+        sh.L = 2 * g.m + 1;
+        sh.B = g.tune_B > 0 ? g.tune_B : stream_band_rows(g.n, g.m, 64 * sh.R, g.nids);
+    }
+    if (sh.B > g.n) sh.B = g.n;
+    sh.per_sample = ((g.n + 64 * sh.R - 1) / (64 * sh.R)) * ((g.n + sh.B - 1) / sh.B);
+    return sh;
 }
 
 // Tile of the direct kernel and the workgroups one sample occupies.

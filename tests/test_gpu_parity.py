@@ -231,26 +231,116 @@ def test_mfmc_estimate_matches_oracle():
         np.testing.assert_allclose(got["mean_mjm1"][1:], ref["mean_mjm1"][1:], rtol=1e-13)
 
 
-def test_autotuned_shapes_give_identical_results():
-    """The streaming kernel's launch shape (columns per lane, band height) does
-    not change any result: every site sums the same window sums in the same
-    row order.  The autotuner times several shapes and keeps one."""
+def _shape_workload(prec="f32", nsteps=9, big=True):
     delta = 1.0 / 32
     amp, sigma, _ = synth.gaussian_params(delta)
     models = [synth.Model(256, delta, 1, amp, sigma, tau=0.01),
               synth.Model(300, 16 / 300, 0, 1.0253 * 300 * 300 / 797, 0.0, tau=0.01),
+              synth.Model(130, 32 / 130, 1, 4e-3 / (math.pi * (32 / 390) ** 4),
+                          32 / 390, tau=0.01),
               synth.Model(1024, 1 / 32, 1, amp, sigma, tau=0.01)]
     samples = [synth.Sample(0, 1.0, amp, "nuclei", 4, s, synth.draw_theta(synth.rng_for(4, s)))
                for s in range(3)]
     samples += [synth.Sample(1, 1.0, models[1].amp, "iid", 7, s) for s in range(2)]
-    samples += [synth.Sample(2, 1.0, amp, "nuclei", 4, 9, synth.draw_theta(synth.rng_for(4, 9)))]
-    w = synth.Workload("shapes", models, samples, 9, "f32")
+    samples += [synth.Sample(2, 1.0, models[2].amp, "iid", 8, s) for s in range(2)]
+    if big:
+        samples += [synth.Sample(3, 1.0, amp, "nuclei", 4, 9,
+                                 synth.draw_theta(synth.rng_for(4, 9)))]
+    else:
+        models = models[:3]
+    return synth.Workload("shapes", models, samples, nsteps, prec)
+
+
+@pytest.fixture
+def reset_shape():
+    yield
+    nlch.nlch_set_stream_shape(0, 0, 0, 0)
+
+
+def test_single_wave_shapes_give_identical_results(reset_shape):
+    """With one wave per band the launch shape (columns per lane, band
+    height) does not change any result: every site sums the same window sums
+    in the same row order."""
+    w = _shape_workload()
+    ref = DeviceBatch(w)
+    ref.solve(nlch.NLCH_ALGO_ROWRUN)
+    torch.cuda.synchronize()
+    for R, B in ((1, 16), (2, 40), (1, 97), (2, 0), (1, 1024)):
+        print("shape R=%d W=1 B=%d" % (R, B), flush=True)
+        nlch.nlch_set_stream_shape(R, 1, 0, B)
+        b = DeviceBatch(w)
+        b.solve(nlch.NLCH_ALGO_ROWRUN)
+        torch.cuda.synchronize()
+        assert torch.equal(ref.state, b.state), (R, B)
+        assert torch.equal(ref.ooi, b.ooi), (R, B)
+
+
+SHAPES_MW = [(1, 2, 1), (2, 2, 2), (1, 4, 1), (2, 4, 1), (1, 8, 1), (1, 4, 4), (2, 8, 2)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("R,W,k", SHAPES_MW)
+def test_multiwave_bands_one_step(orc, reset_shape, R, W, k, prec):
+    """Bands shared by W waves (partial sums handed over in LDS): one step
+    from random states against the oracle on every site, lattices with ragged
+    strips and bands (300^2), a band taller than the lattice, and groups the
+    shared-band kernel is not built for (FP64; 130^2 with m = 32), which use
+    one wave per band; with the energy trace on."""
+    w = _shape_workload(prec, nsteps=1, big=False)
+    print("multiwave R=%d W=%d periods=%d %s" % (R, W, k, prec), flush=True)
+    nlch.nlch_set_stream_shape(R, W, k, 0)
+    b = DeviceBatch(w, prec)
+    rng = np.random.default_rng(5)
+    host = np.clip(rng.uniform(-1.5, 1.5, b.total), -1, 1).astype(NPD[prec])
+    b.state.copy_(torch.from_numpy(host).to(DEV))
+    b.init.copy_(b.state)
+    e = b.solve_energy(nlch.NLCH_ALGO_ROWRUN, nsteps=1)
+    torch.cuda.synchronize()
+    E = e.cpu().numpy()
+    for i, smp in enumerate(w.samples):
+        m = w.models[smp.model]
+        off = b.samples[i].offset
+        u0 = host[off:off + m.n * m.n].astype(np.float64).reshape(m.n, m.n)
+        ref = orc.step(u0, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F, m.beta1, m.tau)
+        got = b.sample_state(i)
+        assert np.max(np.abs(got - ref)) <= ONE_STEP_TOL[prec], (i, m.n)
+        e0 = orc.energy(u0, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F)
+        e1 = orc.energy(got, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F)
+        etol = 1e-11 if prec == "f64" else 1e-5
+        assert abs(E[0, i] - e0) <= etol * abs(e0), (i, E[0, i], e0)
+        assert abs(E[1, i] - e1) <= etol * abs(e1), (i, E[1, i], e1)
+
+
+def test_multiwave_trajectory_and_repeatability(orc, reset_shape):
+    """Nine steps with W = 4 waves per band: the OoI stays within the FP32
+    trajectory bar of the oracle, and the same shape repeats bit-exactly."""
+    w = _shape_workload("f32", nsteps=9)
+    nlch.nlch_set_stream_shape(1, 4, 1, 0)
     a = DeviceBatch(w)
     a.solve(nlch.NLCH_ALGO_ROWRUN)
     b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_ROWRUN)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state, b.state)
+    ref = oracle_samples(orc, w, [0, 3, 5], "f32")
+    o = a.ooi_host()
+    for i in (0, 3, 5):
+        assert abs(o[i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2]), i
+        assert np.max(np.abs(a.sample_state(i) - ref[i][0])) <= 1e-4
+
+
+def test_autotune_is_repeatable(reset_shape):
+    """The autotuner keeps one shape per batch signature: later calls repeat
+    exactly; results stay within rounding of the default shape."""
+    w = _shape_workload()
+    ref = DeviceBatch(w)
+    ref.solve(nlch.NLCH_ALGO_ROWRUN)
+    b = DeviceBatch(w)
     b.solve(nlch.NLCH_ALGO_ROWRUN | nlch.NLCH_ALGO_AUTOTUNE)
+    first = b.state.clone()
     b.reset()
     b.solve(nlch.NLCH_ALGO_ROWRUN | nlch.NLCH_ALGO_AUTOTUNE)
     torch.cuda.synchronize()
-    assert torch.equal(a.state, b.state)
-    assert torch.equal(a.ooi, b.ooi)
+    assert torch.equal(first, b.state)
+    assert torch.max(torch.abs(b.state - ref.state)).item() <= 1e-5
+    np.testing.assert_allclose(b.ooi_host(), ref.ooi_host(), rtol=1e-6)

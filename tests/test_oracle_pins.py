@@ -279,6 +279,33 @@ def test_energy_two_forms_and_monotone_decrease(orc):
     assert abs(e2 - en[-1]) < 1e-12 * max(1.0, abs(e2))
 
 
+@pytest.mark.parametrize("n,r,kind", [(12, 3, 0), (13, 2.5, 1), (20, 4, 0)])
+def test_energy_matches_exactly_rounded_pair_sum(orc, n, r, kind):
+    """E_h against math.fsum over every lattice pair within the horizon
+    (minimum-image distances, no disc tables), on random data."""
+    rng = np.random.default_rng(n)
+    u = rng.uniform(-1, 1, (n, n))
+    delta = r / n
+    sigma, amp, c_F = delta / 3, 3.7, 0.9
+    h = 1.0 / n
+    terms, pot = [], []
+    for y in range(n):
+        for x in range(n):
+            pot.append(1.0 - u[y, x] ** 2)
+            for yy in range(n):
+                for xx in range(n):
+                    dy = min(abs(y - yy), n - abs(y - yy))
+                    dx = min(abs(x - xx), n - abs(x - xx))
+                    if dy * dy + dx * dx > (delta * n) ** 2 + 1e-9:
+                        continue
+                    rr = h * math.sqrt(dy * dy + dx * dx)
+                    g = amp * (math.exp(-rr * rr / sigma ** 2) if kind else 1.0)
+                    terms.append(h * h * g * (u[y, x] - u[yy, xx]) ** 2)
+    exact = h * h * (0.25 * math.fsum(terms) + 0.5 * c_F * math.fsum(pot))
+    got = orc.energy(u, n, delta, kind, amp, sigma, c_F)
+    assert abs(got - exact) <= 1e-14 * abs(exact)
+
+
 def test_output_of_interest_is_fsum_mean(orc):
     w = synth.workload("C1", n=40, nsteps=30)
     m = w.models[0]
