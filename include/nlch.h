@@ -207,7 +207,9 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
  * parameter draw i at y_dev[j][i * y_stride] for i < m[j] (draws shared
  * across models: model j+1 uses draws 0..m[j]-1).  y_stride >= 1; pass 2
  * and &ooi_out[2*s0 + 1] to read the f_1 values of nlch_solve_batch output
- * in place.  m: host array, non-decreasing, m[0] >= 2.
+ * in place.  m: host array, non-decreasing, m[0] >= 2 (m[0] >= 1 when
+ * alpha is given: the below-minimum-budget allocation of Sec. 4 can give
+ * m_1 = 1; var and rho are then NaN).
  * alpha: NULL (estimate alpha_j = rho_{1j} sigma_1 / sigma_j, eq. alpha, from
  * the first m[0] shared draws; zero-variance models get alpha = 0) or K-1 host
  * values for models 2..K.  Moments are accumulated in FP64 on the device
@@ -253,10 +255,10 @@ int mfmc_select(int32_t K, const double *cost, const double *rho, mfmc_subset *o
 int mfmc_allocate(int32_t S, const int32_t *subset, const double *cost, const double *rho,
                   double budget, double *m_real, int64_t *m_int, double *m1_star);
 
-/* The disc sizes R2 for which ROWRUN kernels are compiled (RESIDENT uses the
- * subset with m <= 8): writes up to cap values into r2_list and returns the
- * total count. */
-int nlch_rowrun_supported(int64_t *r2_list, int32_t cap);
+/* The disc sizes R2 for which ROWRUN kernels are compiled for a precision
+ * (NLCH_F*; RESIDENT uses the subset with m <= 8): writes up to cap values
+ * into r2_list and returns the total count, or NLCH_EINVAL.  Host only. */
+int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *nlch_last_error(void);

@@ -31,15 +31,18 @@ def mfmc_estimate(ys, m, alpha=None):
     """Returns a dict with q_mfmc, q_mc, mean_mj, mean_mjm1, var, rho, alpha.
 
     ys: list of K 1-D arrays (model outputs, model 1 first); m: K sample
-    counts, non-decreasing, m[0] >= 2; alpha: None or K-1 coefficients for
-    models 2..K.
+    counts, non-decreasing, m[0] >= 2 (m[0] >= 1 when alpha is given: the
+    below-minimum-budget allocation of Sec. 4 sets m_1 = 1, and the estimator
+    needs only means; var and rho are then NaN); alpha: None or K-1
+    coefficients for models 2..K.
     """
     K = len(ys)
     m = [int(v) for v in m]
     if K < 1 or len(m) != K:
         raise ValueError("need one sample count per model")
-    if m[0] < 2 or any(m[j] < m[j - 1] for j in range(1, K)):
-        raise ValueError("sample counts must be non-decreasing with m[0] >= 2")
+    if m[0] < (1 if alpha is not None else 2) or any(m[j] < m[j - 1] for j in range(1, K)):
+        raise ValueError("sample counts must be non-decreasing with m[0] >= 2 "
+                         "(>= 1 with alpha given)")
     ys = [np.asarray(y, dtype=np.float64) for y in ys]
     for j in range(K):
         if ys[j].size < m[j]:
@@ -55,10 +58,12 @@ def mfmc_estimate(ys, m, alpha=None):
         s = ys[j][:m0]
         c = s - _mean(s)
         centred.append(c)
-        var.append(float(np.sum(c * c) / (m0 - 1)))
+        var.append(float(np.sum(c * c) / (m0 - 1)) if m0 > 1 else float("nan"))
     rho = []
     for j in range(K):
-        if var[0] == 0.0 or var[j] == 0.0:
+        if m0 < 2:
+            rho.append(float("nan"))
+        elif var[0] == 0.0 or var[j] == 0.0:
             rho.append(0.0)
         else:
             cov = float(np.sum(centred[0] * centred[j]) / (m0 - 1))

@@ -51,8 +51,9 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs a, double *__restrict__
         double *o = out + 8 * j;
         o[0] = s_mj / (double)mj;
         o[1] = j > 0 ? s_mjm1 / (double)mjm1 : 0.0;
-        o[2] = sv / (double)(m0 - 1);
-        o[3] = sc / (double)(m0 - 1);
+        // one shared draw (below-minimum-budget allocations): no variance
+        o[2] = m0 > 1 ? sv / (double)(m0 - 1) : __builtin_nan("");
+        o[3] = m0 > 1 ? sc / (double)(m0 - 1) : __builtin_nan("");
         o[4] = mean0j;
     }
 }

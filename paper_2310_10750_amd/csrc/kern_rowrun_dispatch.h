@@ -7,8 +7,16 @@
 
 namespace nlch {
 
-// Horizons (as R2 = floor((delta n)^2)) with compiled row-run kernels.
-#define NLCH_ROWRUN_R2_LIST(X) X(1) X(4) X(9) X(16) X(25) X(64) X(256) X(272) X(1024)
+// Horizons (as R2 = floor((delta n)^2)) with compiled row-run kernels: the
+// recipes' horizons for every type pair, plus (units that define
+// NLCH_ROWRUN_EXTRA_R2 before including this header) the other horizons of
+// the nine (h, delta) models of the multifidelity study in Sec. 4
+// (delta n = 11, 12, 22, 24).
+#ifndef NLCH_ROWRUN_EXTRA_R2
+#define NLCH_ROWRUN_EXTRA_R2(X)
+#endif
+#define NLCH_ROWRUN_R2_LIST(X) \
+    X(1) X(4) X(9) X(16) X(25) X(64) X(256) X(272) X(1024) NLCH_ROWRUN_EXTRA_R2(X)
 #define NLCH_RESIDENT_R2_LIST(X) X(1) X(4) X(9) X(16) X(25) X(64)
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -148,9 +156,16 @@ hipError_t resident_typed(const Group &g, void *state, int nsteps, double *ooi,
 
 }  // namespace nlch
 
+#define NLCH_R2_ITEM(v) v,
 // Defines the entry points of one type pair under the given suffix.
 #define NLCH_ROWRUN_UNIT(SUFFIX, TS, TA)                                                    \
     namespace nlch {                                                                        \
+    int rowrun_r2_##SUFFIX(int64_t *out, int cap) {                                         \
+        const int64_t list[] = {NLCH_ROWRUN_R2_LIST(NLCH_R2_ITEM)};                         \
+        const int cnt = (int)(sizeof(list) / sizeof(list[0]));                              \
+        for (int i = 0; i < cnt && i < cap; ++i) out[i] = list[i];                          \
+        return cnt;                                                                         \
+    }                                                                                       \
     bool rowrun_has_##SUFFIX(int R2) { return rowrun_has_typed<TS, TA>(R2); }               \
     bool resident_has_##SUFFIX(int R2, int n) { return resident_has_typed<TS, TA>(R2, n); } \
     hipError_t rowrun_step_##SUFFIX(const Group &g, const void *in, void *out,              \

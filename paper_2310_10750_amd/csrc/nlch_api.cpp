@@ -22,6 +22,7 @@
 namespace nlch {
 // per-type-pair units (kern_rowrun_*.hip)
 #define NLCH_DECL(SUF)                                                                   \
+    int rowrun_r2_##SUF(int64_t *out, int cap);                                          \
     bool rowrun_has_##SUF(int R2);                                                       \
     bool resident_has_##SUF(int R2, int n);                                              \
     hipError_t rowrun_step_##SUF(const Group &g, const void *in, void *out, hipStream_t s, \
@@ -70,11 +71,12 @@ hipError_t launch_resident(int prec, bool, const Group &g, void *state, int nste
     }
 }
 
-int rowrun_r2_list(int64_t *out, int cap) {
-    static const int64_t list[] = {1, 4, 9, 16, 25, 64, 256, 272, 1024};
-    const int cnt = (int)(sizeof(list) / sizeof(list[0]));
-    for (int i = 0; i < cnt && i < cap; ++i) out[i] = list[i];
-    return cnt;
+int rowrun_r2_list(int prec, int64_t *out, int cap) {
+    switch (prec) {
+        case kF64: return rowrun_r2_f64(out, cap);
+        case kF32: return rowrun_r2_f32(out, cap);
+        default: return rowrun_r2_f16(out, cap);
+    }
 }
 
 }  // namespace nlch
@@ -807,9 +809,11 @@ int nlch_version(void) { return 3; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 
-int nlch_rowrun_supported(int64_t *r2_list, int32_t cap) {
+int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap) {
+    if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
+        return fail(NLCH_EINVAL, "unknown precision %d", precision);
     if (cap < 0 || (cap > 0 && !r2_list)) return fail(NLCH_EINVAL, "bad output array");
-    return rowrun_r2_list(r2_list, cap);
+    return rowrun_r2_list(precision, r2_list, cap);
 }
 
 int nlch_disc(int32_t n, double delta, int64_t *R2, int32_t *m, int64_t *N, int32_t *halfw,
@@ -929,7 +933,8 @@ int mfmc_estimate(int32_t K, const int64_t *m, const double *const *y_dev, int64
     if (K < 1 || K > NLCH_MFMC_MAX_K)
         return fail(NLCH_EINVAL, "K must be in [1, %d]", NLCH_MFMC_MAX_K);
     if (!m || !y_dev || !out) return fail(NLCH_EINVAL, "m, y_dev and out must be non-NULL");
-    if (m[0] < 2) return fail(NLCH_EINVAL, "m[0] must be >= 2");
+    if (m[0] < (alpha ? 1 : 2))
+        return fail(NLCH_EINVAL, alpha ? "m[0] must be >= 1" : "m[0] must be >= 2 without alpha");
     if (y_stride < 1) return fail(NLCH_EINVAL, "y_stride must be >= 1");
     for (int j = 1; j < K; ++j)
         if (m[j] < m[j - 1]) return fail(NLCH_EINVAL, "sample counts must be non-decreasing");

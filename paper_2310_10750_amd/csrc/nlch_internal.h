@@ -164,7 +164,7 @@ hipError_t launch_moments(int K, const double *const *y, const int64_t *m,
 // returns code.
 int set_error(int code, const char *msg);
 
-// List of R2 values with compiled row-run kernels.
-int rowrun_r2_list(int64_t *out, int cap);
+// List of R2 values with compiled row-run kernels for a precision.
+int rowrun_r2_list(int prec, int64_t *out, int cap);
 
 }  // namespace nlch

@@ -118,7 +118,7 @@ def load():
     lib.mfmc_allocate.argtypes = [i32, ctypes.POINTER(i32), pd, pd, ctypes.c_double, pd,
                                   ctypes.POINTER(i64), pd]
     lib.mfmc_allocate.restype = ctypes.c_int
-    lib.nlch_rowrun_supported.argtypes = [ctypes.POINTER(i64), i32]
+    lib.nlch_rowrun_supported.argtypes = [i32, ctypes.POINTER(i64), i32]
     lib.nlch_rowrun_supported.restype = ctypes.c_int
     lib.nlch_last_error.argtypes = []
     lib.nlch_last_error.restype = ctypes.c_char_p
@@ -157,10 +157,11 @@ def nlch_version() -> int:
     return load().nlch_version()
 
 
-def nlch_rowrun_supported():
+def nlch_rowrun_supported(precision: int = 1):
+    """R2 values with row-run kernels for a precision (default NLCH_F32)."""
     lib = load()
     buf = (ctypes.c_int64 * 64)()
-    cnt = lib.nlch_rowrun_supported(buf, 64)
+    cnt = lib.nlch_rowrun_supported(precision, buf, 64)
     _check(0 if cnt >= 0 else cnt)
     return [buf[i] for i in range(min(cnt, 64))]
 

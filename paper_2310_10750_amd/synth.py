@@ -117,6 +117,36 @@ def ic_nuclei(n: int, theta) -> np.ndarray:
     return u
 
 
+def theta_block(seed: int, block: int, size: int = 4096) -> np.ndarray:
+    """Nuclei parameters of samples block*size .. block*size+size-1 of a
+    large study (one generator per block of draws): rows (mu1, eta1x, eta1y,
+    ..., mu4, eta4x, eta4y) with mu ~ U[0.9, 1], eta ~ U[-0.025, 0.025]."""
+    u = rng_for(seed, block).uniform(size=(size, 12))
+    lo = np.tile([0.9, -0.025, -0.025], 4)
+    width = np.tile([0.1, 0.05, 0.05], 4)
+    return lo + width * u
+
+
+def ic_nuclei_batch(n: int, thetas, device="cuda:0"):
+    """Eq. ic for a batch of parameter rows (as theta_block), computed with
+    torch on `device` in FP64: a (B, n*n) tensor, not projected.  Same formula
+    and minimum-image distance as ic_nuclei."""
+    import torch
+    th = torch.as_tensor(np.asarray(thetas, dtype=np.float64), device=device)
+    coords = torch.arange(n, dtype=torch.float64, device=device) / n
+    X = coords[None, None, :]
+    Y = coords[None, :, None]
+    u = torch.ones((th.shape[0], n, n), dtype=torch.float64, device=device)
+    for i, (cx, cy) in enumerate(NUCLEI_CENTRES):
+        mu = th[:, 3 * i, None, None]
+        dx = X - (cx + th[:, 3 * i + 1, None, None])
+        dy = Y - (cy + th[:, 3 * i + 2, None, None])
+        dx = dx - torch.round(dx)
+        dy = dy - torch.round(dy)
+        u = u - 2.0 * mu * torch.exp(-36.0 * (dx * dx + dy * dy))
+    return u.reshape(th.shape[0], n * n)
+
+
 def initial_state(w: Workload, s: Sample) -> np.ndarray:
     n = w.models[s.model].n
     if s.ic == "iid":

@@ -50,13 +50,22 @@ def test_disc_tables_bit_exact_with_oracle(orc, n, delta):
 
 
 def test_rowrun_r2_list_covers_recipes():
-    r2 = set(nlch.nlch_rowrun_supported())
-    for name in ("C1", "C2", "C3", "C5"):
-        w = synth.workload(name, n_samples=1, nsteps=1)
-        m = w.models[0]
+    for prec in (nlch.NLCH_F64, nlch.NLCH_F32, nlch.NLCH_F16_STORE):
+        r2 = set(nlch.nlch_rowrun_supported(prec))
+        for name in ("C1", "C2", "C3", "C5"):
+            w = synth.workload(name, n_samples=1, nsteps=1)
+            m = w.models[0]
+            assert nlch.nlch_disc(m.n, m.delta)[0] in r2
+        for m in synth.workload("C4", n_samples=4, nsteps=1).models:
+            assert nlch.nlch_disc(m.n, m.delta)[0] in r2
+    # FP32 arithmetic also covers the nine (h, delta) models of the MFMC study
+    from paper_2310_10750_amd import mfmc_study
+    r2 = set(nlch.nlch_rowrun_supported(nlch.NLCH_F32))
+    for m in mfmc_study.study_models():
         assert nlch.nlch_disc(m.n, m.delta)[0] in r2
-    for m in synth.workload("C4", n_samples=4, nsteps=1).models:
-        assert nlch.nlch_disc(m.n, m.delta)[0] in r2
+    assert set(nlch.nlch_rowrun_supported(nlch.NLCH_F16_STORE)) == r2
+    with pytest.raises(nlch.NlchError):
+        nlch.nlch_rowrun_supported(9)
 
 
 @pytest.mark.parametrize("kind", [0, 1])

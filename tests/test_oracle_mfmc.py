@@ -104,3 +104,15 @@ def test_zero_variance_model_gets_zero_alpha():
     r = mfmc.mfmc_estimate([y1, y2], m)
     assert r["alpha"][1] == 0.0 and r["rho"][1] == 0.0
     assert r["q_mfmc"] == r["q_mc"]
+
+
+def test_single_shared_draw_with_given_alpha():
+    """The below-minimum-budget allocation of Sec. 4 can give m_1 = 1; with
+    alpha given the estimator needs only means (variance and correlation are
+    undefined)."""
+    ys = [np.array([2.0]), np.array([1.0, 2.0, 3.0]), np.array([5.0, 1.0, 0.0, 4.0])]
+    r = mfmc.mfmc_estimate(ys, [1, 3, 4], [0.5, 0.25])
+    assert r["q_mfmc"] == 2.0 + 0.5 * (2.0 - 1.0) + 0.25 * (2.5 - 2.0)
+    assert math.isnan(r["var"][0]) and math.isnan(r["rho"][1])
+    with pytest.raises(ValueError):
+        mfmc.mfmc_estimate(ys, [1, 3, 4])
