@@ -20,6 +20,20 @@
  *     c1 = tau beta1 / (1 + tau beta1 xi_h),   u' = clamp(v, -1, 1).
  * The output of interest is f_1 = (1 + mean(u^T)) / 2 (eq. ooi).
  *
+ * With beta2 > 0 (eq. nonl_CH_nm with both terms, du/dt + A w = 0,
+ * A = beta1 I - beta2 Delta; Delta_h the periodic 5-point Laplacian of lumped
+ * P1 elements) each step solves the coupled variational inequality
+ *     u + tau A (xi_h u + mu) = u^{k-1} + tau A (gamma*u^{k-1}),
+ *     mu in the normal cone of [-1, 1]^{n^2} at u,
+ * which for xi_h > 0 has a unique solution: with z = xi_h u + mu,
+ * u = clamp(z / xi_h) and z is the root of a strictly convex gradient, found
+ * by semismooth Newton with conjugate-gradient inner solves (FP64, one
+ * workgroup per sample, n <= 256).  Models with beta2 > 0 and a sample with
+ * xi_h <= 0 (a non-convex step with possibly several solutions) are
+ * NLCH_EUNSUPPORTED.  A sample whose Newton iteration does not converge
+ * within its iteration cap gets a NaN state and output of interest.
+ * Per sample the library keeps 7 n^2 doubles of workspace with the batch.
+ *
  * Conventions for every entry point:
  *  - Status: 0 on success, else one of the NLCH_E* codes; the message of the
  *    last failure on the calling thread is returned by nlch_last_error().
@@ -96,7 +110,7 @@ typedef struct nlch_model {
     double kernel_sigma; /* Gaussian width > 0 (ignored for the constant kernel)*/
     double c_F;          /* obstacle-potential constant > 0                     */
     double beta1;        /* > 0                                                 */
-    double beta2;        /* must be 0 (else NLCH_EUNSUPPORTED)                  */
+    double beta2;        /* >= 0; > 0 needs n <= 256 and xi_h > 0 per sample   */
     double tau;          /* time step > 0 with 1 + tau beta1 xi_h > 0           */
 } nlch_model;
 

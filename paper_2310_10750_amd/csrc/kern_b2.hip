@@ -1,0 +1,256 @@
+// The time step with beta2 > 0: eq. nonl_CH_nm with beta1 > 0 and beta2 > 0
+// (the non-mass-conserving model of the paper's experiments), discretised as
+// in Sec. 4 -- implicit Euler with the convolution explicit, nodal
+// quadrature of the convolution, A = beta1 I - beta2 Delta_h with the
+// periodic 5-point Laplacian (lumped P1 elements on the uniform mesh):
+//
+//     u + tau A (xi u + mu) = r,   r = u_old + tau A g,   g = gamma * u_old,
+//     mu in the normal cone of K = [-1, 1]^{n^2} at u.
+//
+// For xi > 0 write z = xi u + mu: then u = P_K(z / xi), and z is the root of
+// F(z) = tau A z + P_K(z / xi) - r, the gradient of the strictly convex
+// Phi(z) = tau/2 z'Az + sum_i phi(z_i) - r'z with phi(s) = s^2/(2 xi) for
+// |s| <= xi and |s| - xi/2 otherwise, so the step is unique.  Semismooth
+// Newton on F: the Jacobian tau A + diag(1/xi where |z| < xi) is symmetric
+// positive definite and each system is solved by conjugate gradients with
+// the matrix-free 5-point stencil; the step length comes from Armijo
+// backtracking on Phi.  Newton starts from z = xi u_old, so a step depends on
+// u_old only.
+//
+// One workgroup per sample, FP64 throughout, vectors in a per-sample global
+// workspace.  Every decision is taken on block-reduced scalars, so control
+// flow is uniform across the workgroup; every loop has a fixed cap, and a
+// sample whose Newton iteration has not converged at the cap gets a NaN
+// state (hence a NaN output of interest).
+#include "nlch_device.h"
+
+namespace nlch {
+
+namespace {
+
+constexpr int kB2Threads = 256;
+constexpr int kB2Waves = kB2Threads / 64;
+constexpr int kMaxNewton = 40;
+constexpr int kMaxCg = 4000;
+constexpr int kMaxHalvings = 30;
+
+__device__ __forceinline__ double clampd(double v) {
+    return v < -1.0 ? -1.0 : (v > 1.0 ? 1.0 : v);
+}
+
+__device__ __forceinline__ double phi(double s, double xi) {
+    const double a = fabs(s);
+    return a <= xi ? s * s / (2.0 * xi) : a - 0.5 * xi;
+}
+
+// (tau A v)_i = tau beta1 v_i - tau beta2 n^2 (v_E + v_W + v_N + v_S - 4 v_i),
+// periodic neighbours of site i = y n + x.
+__device__ __forceinline__ double tau_a(const double *v, int i, int y, int x, int n, int nn,
+                                        double tb1, double tb2n2) {
+    const int ie = x + 1 < n ? i + 1 : i + 1 - n;
+    const int iw = x > 0 ? i - 1 : i - 1 + n;
+    const int in_ = y + 1 < n ? i + n : i + n - nn;
+    const int is = y > 0 ? i - n : i - n + nn;
+    const double c = v[i];
+    return tb1 * c - tb2n2 * (v[ie] + v[iw] + v[in_] + v[is] - 4.0 * c);
+}
+
+// K block-wide FP64 sums in a fixed order (shuffle tree, then the waves in
+// order); every thread receives the results.  `red` holds kB2Waves * K.
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double *red) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();  // the previous use of red is over; this call's stores are done
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < kB2Waves; ++i) s += red[i * K + k];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ double block_sum1(double v, double *red) {
+    double a[1] = {v};
+    block_sums<1>(a, red);
+    return a[0];
+}
+
+template <class TS, bool GAUSS>
+__global__ __launch_bounds__(kB2Threads) void k_b2_step(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
+    const TS *__restrict__ in, TS *__restrict__ out, double *__restrict__ ws,
+    double *__restrict__ epart) {
+    __shared__ double red[kB2Waves * 4];
+    const int j = blockIdx.x;
+    const SampleDesc d = sd[ids[j]];
+    const int n = geo->n, m = geo->m;
+    const int nn = n * n;
+    const TS *u = in + d.offset;
+    TS *uo = out + d.offset;
+    double *R = ws + (int64_t)j * 7 * nn;  // right-hand side r
+    double *Z = R + nn;                    // Newton iterate z
+    double *F = Z + nn;                    // F(z)
+    double *X = F + nn;                    // Newton direction
+    double *S = X + nn;                    // CG residual
+    double *P = S + nn;                    // CG direction
+    double *Q = P + nn;                    // g, then operator products
+    const double xi = d.xi;
+    const double tb1 = geo->tau_b1, tb2n2 = geo->tau_b2 * (double)nn;
+    const double gs = 2.0 * d.e_int * (double)nn;  // h^2 amp
+    const double *e = ewd + geo->e_off;
+    const int tid = threadIdx.x;
+
+    // g = h^2 amp sum_{d in D} e_d u_{i+d}; energy partials of u_old
+    double e_ul = 0.0, e_pot = 0.0;
+    for (int i = tid; i < nn; i += kB2Threads) {
+        const int y = i / n, x = i - y * n;
+        const double ui = (double)u[i];
+        double acc = 0.0, lsum = 0.0;
+        for (int dy = -m; dy <= m; ++dy) {
+            const int ady = dy < 0 ? -dy : dy;
+            const int w = geo->halfw[ady];
+            const TS *row = u + (int64_t)wrap_once(y + dy, n) * n;
+            for (int dx = -w; dx <= w; ++dx) {
+                const double v = (double)row[wrap_once(x + dx, n)];
+                const double wt = GAUSS ? e[ady * (m + 1) + (dx < 0 ? -dx : dx)] : 1.0;
+                acc += wt * v;
+                lsum += wt * (ui - v);
+            }
+        }
+        Q[i] = gs * acc;
+        e_ul += ui * lsum;
+        e_pot += 1.0 - ui * ui;
+    }
+    if (epart) {
+        double v[2] = {e_ul, e_pot};
+        block_sums<2>(v, red);
+        if (tid == 0) {
+            epart[2 * (int64_t)j] = v[0];
+            epart[2 * (int64_t)j + 1] = v[1];
+        }
+    }
+    __syncthreads();
+    // r = u_old + tau A g, z = xi u_old
+    double rr = 0.0;
+    for (int i = tid; i < nn; i += kB2Threads) {
+        const int y = i / n, x = i - y * n;
+        const double ui = (double)u[i];
+        const double r = ui + tau_a(Q, i, y, x, n, nn, tb1, tb2n2);
+        R[i] = r;
+        Z[i] = xi * ui;
+        rr += r * r;
+    }
+    const double scale = fmax(1.0, sqrt(block_sum1(rr, red)));
+
+    bool ok = false;
+    for (int it = 0;; ++it) {
+        // F(z); converged when |F| <= 1e-13 max(1, |r|)
+        double f2 = 0.0;
+        for (int i = tid; i < nn; i += kB2Threads) {
+            const int y = i / n, x = i - y * n;
+            const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(Z[i] / xi) - R[i];
+            F[i] = f;
+            X[i] = 0.0;
+            S[i] = -f;
+            P[i] = -f;
+            f2 += f * f;
+        }
+        f2 = block_sum1(f2, red);
+        if (sqrt(f2) <= 1e-13 * scale) {
+            ok = true;
+            break;
+        }
+        if (it == kMaxNewton) break;
+        // conjugate gradients on J x = -F (x0 = 0), relative tolerance
+        // min(1e-2, |F| / scale) (inexact Newton: superlinear near the root)
+        const double eta = fmin(1e-2, sqrt(f2) / scale);
+        const double stop = eta * eta * f2;
+        double rs = f2;
+        for (int k = 0; k < kMaxCg && rs > stop; ++k) {
+            double pq = 0.0;
+            for (int i = tid; i < nn; i += kB2Threads) {
+                const int y = i / n, x = i - y * n;
+                const double q = tau_a(P, i, y, x, n, nn, tb1, tb2n2) +
+                                 (fabs(Z[i]) < xi ? P[i] / xi : 0.0);
+                Q[i] = q;
+                pq += P[i] * q;
+            }
+            pq = block_sum1(pq, red);
+            if (!(pq > 0.0)) break;
+            const double alpha = rs / pq;
+            double rn = 0.0;
+            for (int i = tid; i < nn; i += kB2Threads) {
+                X[i] += alpha * P[i];
+                const double sv = S[i] - alpha * Q[i];
+                S[i] = sv;
+                rn += sv * sv;
+            }
+            rn = block_sum1(rn, red);
+            const double beta = rn / rs;
+            rs = rn;
+            for (int i = tid; i < nn; i += kB2Threads) P[i] = S[i] + beta * P[i];
+            __syncthreads();
+        }
+        // Armijo backtracking on Phi along x:
+        // Phi(z + a x) - Phi(z) = a s1 + a^2/2 s2 + sum(phi(z + a x) - phi(z)) - a s3
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = tid; i < nn; i += kB2Threads) {
+            const int y = i / n, x = i - y * n;
+            const double taz = F[i] - clampd(Z[i] / xi) + R[i];
+            const double tax = tau_a(X, i, y, x, n, nn, tb1, tb2n2);
+            sm[0] += X[i] * taz;
+            sm[1] += X[i] * tax;
+            sm[2] += R[i] * X[i];
+            sm[3] += F[i] * X[i];
+        }
+        block_sums<4>(sm, red);
+        double a = 1.0;
+        for (int h = 0; h < kMaxHalvings; ++h) {
+            double dp = 0.0;
+            for (int i = tid; i < nn; i += kB2Threads)
+                dp += phi(Z[i] + a * X[i], xi) - phi(Z[i], xi);
+            dp = block_sum1(dp, red);
+            if (a * sm[0] + 0.5 * a * a * sm[1] + dp - a * sm[2] <= 1e-4 * a * sm[3]) break;
+            a *= 0.5;
+        }
+        for (int i = tid; i < nn; i += kB2Threads) Z[i] += a * X[i];
+        __syncthreads();
+    }
+    const double nan = __builtin_nan("");
+    for (int i = tid; i < nn; i += kB2Threads)
+        uo[i] = to_store<TS>(ok ? clampd(Z[i] / xi) : nan);
+}
+
+template <class TS>
+hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, double *epart) {
+    dim3 grid((unsigned)g.nids), block(kB2Threads);
+    if (g.kernel == 1)
+        hipLaunchKernelGGL((k_b2_step<TS, true>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
+                           (const TS *)in, (TS *)out, g.ws, epart);
+    else
+        hipLaunchKernelGGL((k_b2_step<TS, false>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
+                           (const TS *)in, (TS *)out, g.ws, epart);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, hipStream_t s,
+                          double *epart) {
+    if (!g.ws || g.n > kB2MaxN) return hipErrorInvalidValue;
+    switch (prec) {
+        case kF64: return b2_typed<double>(g, in, out, s, epart);
+        case kF32: return b2_typed<float>(g, in, out, s, epart);
+        default: return b2_typed<half_t>(g, in, out, s, epart);
+    }
+}
+
+}  // namespace nlch

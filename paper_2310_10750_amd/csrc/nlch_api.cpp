@@ -143,9 +143,9 @@ static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) 
     if (!finite_pos(md.beta1)) return fail(NLCH_EINVAL, "%s: beta1 must be > 0", what);
     if (!std::isfinite(md.beta2) || md.beta2 < 0.0)
         return fail(NLCH_EINVAL, "%s: beta2 must be finite and >= 0", what);
-    if (md.beta2 != 0.0)
-        return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 needs a coupled solve per step; "
-                    "this build implements beta2 = 0", what);
+    if (md.beta2 > 0.0 && md.n > kB2MaxN)
+        return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 is built for n <= %d (one workgroup "
+                    "per sample)", what, kB2MaxN);
     if (!finite_pos(md.tau)) return fail(NLCH_EINVAL, "%s: tau must be > 0", what);
 
     const double r = md.delta * (double)md.n;
@@ -202,6 +202,9 @@ static int sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, do
     const double den = 1.0 + tb * c.xi_h;
     if (!(den > 0.0))
         return fail(NLCH_EINVAL, "%s: 1 + tau*beta1*xi_h = %g must be > 0", what, den);
+    if (md.beta2 > 0.0 && !(c.xi_h > 0.0))
+        return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 needs xi_h = c_gamma_h - c_F > 0 (the "
+                    "step is then a strictly convex problem); xi_h = %g", what, c.xi_h);
     c.c1 = tb / den;
     c.a = c.c1 * c_F;
     c.b = c.c1 * h2 * amp;
@@ -226,6 +229,7 @@ struct Batch {
     DevBuf geo, ewf, ewd, sd, ids, partial;
     DevBuf epart;                        // energy partial sums (allocated on demand)
     size_t epart_cap = 0;                // doubles in epart
+    DevBuf b2ws;                         // beta2 > 0 workspaces (allocated on demand)
     std::vector<Group> groups;           // launch groups
     std::vector<int> variant;            // per group
     bool tuned = false;
@@ -289,6 +293,13 @@ float rne_f32(double v) { return (float)v; }
 // Chooses the kernel variant for a model under the requested algorithm.
 int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nlch_model &md,
                    bool batch, int *variant) {
+    if (md.beta2 > 0.0) {
+        // the coupled step has one kernel, whatever the algorithm word asks
+        if (base == NLCH_ALGO_RESIDENT)
+            return fail(NLCH_EUNSUPPORTED, "RESIDENT is built for beta2 = 0 only");
+        *variant = kB2;
+        return NLCH_OK;
+    }
     const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n);
     const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
     switch (base) {
@@ -362,6 +373,8 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         gm.e_off = (int64_t)ewd.size();
         gm.ced = mi[i].ce_sep;
         gm.cef = rne_f32(mi[i].ce_sep);
+        gm.tau_b1 = models[i].tau * models[i].beta1;
+        gm.tau_b2 = models[i].tau * models[i].beta2;
         for (int k = 0; k <= mi[i].m; ++k) {
             gm.gd[k] = mi[i].g[k];
             gm.gf[k] = rne_f32(mi[i].g[k]);
@@ -393,6 +406,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         const double h2 = 1.0 / ((double)d.n * d.n);
         d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
         d.e_pot = 0.5 * h2 * sm.c_F;
+        d.xi = c.xi_h;
     }
     // Groups: per model, samples in batch order.
     std::vector<std::vector<int32_t>> per_model(n_models);
@@ -543,12 +557,32 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
 hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
                        void *out, hipStream_t s, double *epart = nullptr) {
     if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s, epart);
+    if (variant == kB2) return launch_b2_step(prec, g, in, out, s, epart);
     return launch_direct_step(prec, acc64, g, in, out, s, epart);
+}
+
+// Workspaces of the beta2 > 0 groups (b2_ws_doubles(n) per sample), allocated
+// on first use and kept with the batch.
+int ensure_b2ws(Batch &b) {
+    size_t need = 0;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi)
+        if (b.variant[gi] == kB2)
+            need += (size_t)b2_ws_doubles(b.groups[gi].n) * b.groups[gi].nids;
+    if (need == 0 || b.b2ws.p) return NLCH_OK;
+    HIP_TRY(hipMalloc(&b.b2ws.p, sizeof(double) * need));
+    size_t off = 0;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi)
+        if (b.variant[gi] == kB2) {
+            b.groups[gi].ws = reinterpret_cast<double *>(b.b2ws.p) + off;
+            off += (size_t)b2_ws_doubles(b.groups[gi].n) * b.groups[gi].nids;
+        }
+    return NLCH_OK;
 }
 
 // Workgroups one sample of a streaming group occupies per step launch.
 int step_blocks_per_sample(int variant, const Group &g) {
     if (variant == kRowrun) return stream_shape(g).per_sample;
+    if (variant == kB2) return 1;
     return direct_tiles(g.n);
 }
 
@@ -760,6 +794,8 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         rc = ensure_epart(*b);
         if (rc) return rc;
     }
+    rc = ensure_b2ws(*b);
+    if (rc) return rc;
 
     if (algo & NLCH_ALGO_NOGRAPH)
         return enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
@@ -896,6 +932,8 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     if (rc) return rc;
     const bool acc64 = (algo & NLCH_ALGO_ACC64) != 0 || precision == kF64;
     hipStream_t s = (hipStream_t)hip_stream;
+    rc = ensure_b2ws(*b);
+    if (rc) return rc;
     const Group &g = b->groups[0];
     HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
     if (ooi_out) HIP_TRY(launch_ooi(precision, g, u_out, ooi_out, 2, s));

@@ -24,6 +24,7 @@ struct ModelGeo {
     int32_t kernel, pad0;
     int64_t e_off;
     double ced;
+    double tau_b1, tau_b2;  // tau beta1, tau beta2 (the beta2 > 0 step)
     float cef, pad1;
     float gf[kMaxM + 1];
     double gd[kMaxM + 1];
@@ -35,6 +36,7 @@ struct ModelGeo {
 //   a = c1 c_F,  b = c1 h^2 amp,  c1 = tau beta1 / (1 + tau beta1 xi_h).
 // Energy factors: E_h(u) = e_int sum_i u_i Lsum_i + e_pot sum_i (1 - u_i^2)
 //   with e_int = h^4 amp / 2 and e_pot = h^2 c_F / 2.
+// xi = xi_h = c_gamma_h - c_F of the sample (used by the beta2 > 0 step).
 struct SampleDesc {
     int64_t offset;   // element offset of the sample's n x n state
     int32_t model;
@@ -42,7 +44,7 @@ struct SampleDesc {
     double a, b;
     float af, bf;
     double e_int, e_pot;
-    int64_t pad;
+    double xi;
 };
 
 // One launch group: samples of one model, processed by one kernel variant.
@@ -53,6 +55,7 @@ struct Group {
     const SampleDesc *sd;   // device pointer to all sample descriptors
     const int32_t *ids;     // device pointer to this group's sample indices
     double *partial;        // device scratch: ooi_chunks(n) doubles per sample
+    double *ws;             // beta2 > 0 groups: b2_ws_doubles(n) doubles per sample
     int32_t nids;
     int32_t n, m, R2;
     int32_t kernel;
@@ -129,7 +132,13 @@ constexpr int kDirTX = 64, kDirTY = 16;
 inline int direct_tiles(int n) { return ((n + kDirTX - 1) / kDirTX) * ((n + kDirTY - 1) / kDirTY); }
 
 // Kernel variants.
-enum Variant { kDirect = 1, kRowrun = 2, kResident = 3 };
+enum Variant { kDirect = 1, kRowrun = 2, kResident = 3, kB2 = 4 };
+
+// The beta2 > 0 step: largest lattice, per-sample FP64 workspace (seven
+// n x n vectors: right-hand side, z, F, Newton direction, CG residual, CG
+// direction, operator product).
+constexpr int kB2MaxN = 256;
+inline int64_t b2_ws_doubles(int n) { return 7 * (int64_t)n * n; }
 
 // Launch wrappers (return the launch status).  `acc64` selects FP64
 // accumulation for the F32/F16 storage types (always on for F64).
@@ -154,6 +163,11 @@ bool resident_supported(int prec, bool acc64, int R2, int kernel, int n);
 hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
                            int nsteps, double *ooi, hipStream_t s,
                            double *energy = nullptr, int64_t estride = 0);
+// One beta2 > 0 step of every sample of the group (one workgroup per sample,
+// workspace g.ws); epart (nullable) receives one energy partial pair per
+// sample.
+hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, hipStream_t s,
+                          double *epart);
 // Per sample of the group, the workgroup partials in order -> energy[ids[j]].
 hipError_t launch_energy_final(const Group &g, const double *epart, int per_sample,
                                double *energy, hipStream_t s);

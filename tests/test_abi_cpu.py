@@ -172,3 +172,28 @@ def test_mfmc_argument_errors():
     assert _err(f, [4096, 8192], [5, 4]) == E
     assert _err(f, [4096, None], [2, 4]) == E
     assert _err(f, [4096, 8192], [2, 4], [float("nan")]) == E
+
+
+def test_beta2_validation():
+    """beta2 > 0 is accepted for xi_h > 0 and n <= 256, rejected (before any
+    device work) for a non-convex step, a larger lattice or RESIDENT."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    ok = nlch.make_model(32, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01)
+    c, xi, c1 = nlch.nlch_model_constants(ok)
+    assert xi > 0
+    nc = nlch.make_model(32, 0.125, 1, amp, sigma, beta2=0.05, tau=0.01)
+    assert _err(nlch.nlch_model_constants, nc) == nlch.NLCH_EUNSUPPORTED
+    assert "xi_h" in nlch.nlch_last_error()
+    big = nlch.make_model(512, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01)
+    assert _err(nlch.nlch_model_constants, big) == nlch.NLCH_EUNSUPPORTED
+    neg = nlch.make_model(32, 0.25, 1, amp, sigma, beta2=-0.05, tau=0.01)
+    assert _err(nlch.nlch_model_constants, neg) == nlch.NLCH_EINVAL
+    S = [nlch.nlch_sample(0, 0, 1.0, amp, 0)]
+    b = 1 << 30
+    assert _err(nlch.nlch_solve_batch, [ok], S, 5, 1, nlch.NLCH_ALGO_RESIDENT, b, 2 * b,
+                3 * b) == nlch.NLCH_EUNSUPPORTED
+    assert _err(nlch.nlch_solve_batch, [ok], S, 5, 1, 0, b, None, 3 * b) == nlch.NLCH_EINVAL
+    # a sample whose own c_F makes xi_h <= 0
+    S2 = [nlch.nlch_sample(0, 0, 1.5, amp, 0)]
+    assert _err(nlch.nlch_solve_batch, [ok], S2, 5, 1, 0, b, 2 * b,
+                3 * b) == nlch.NLCH_EUNSUPPORTED

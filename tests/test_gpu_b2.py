@@ -1,0 +1,141 @@
+"""GPU parity of the beta2 > 0 step (eq. nonl_CH_nm with beta1, beta2 > 0)
+against the FP64 oracle (oracle.b2), through the C ABI.
+
+Both sides solve the same strictly convex step (xi_h > 0) to a residual of
+~1e-13 relative, so FP64 states agree to 1e-10; FP32 and FP16 storage add the
+rounding of the stored state (bars 1e-6 and 1e-3, as for beta2 = 0)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import b2
+from paper_2310_10750_amd import nlch, synth
+from tests.gpu_harness import DeviceBatch, rounded_initial
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TDT = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}
+NPD = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+TOL = {"f64": 1e-10, "f32": 1e-6, "f16": 1e-3}
+
+
+def _amp_for(orc, n, delta, kind, sigma, xi):
+    return (1.0 + xi) / orc.constants(n, delta, kind, 1.0, sigma, 1.0)[0]
+
+
+def _rand(n, seed, prec):
+    rng = np.random.default_rng(seed)
+    u = np.clip(rng.uniform(-1.5, 1.5, (n, n)), -1, 1)
+    return u.astype(NPD[prec]).astype(np.float64)
+
+
+CASES = [(16, 4, 0, 0.05), (24, 9, 1, 0.03), (40, 16, 1, 0.08), (64, 64, 0, 0.0253),
+         (50, 25, 1, 0.02), (96, 64, 1, 0.0253)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("n,R2,kind,xi", CASES)
+def test_b2_one_step(orc, n, R2, kind, xi, prec):
+    print("b2 one-step n=%d R2=%d kernel=%d %s" % (n, R2, kind, prec), flush=True)
+    delta = math.sqrt(R2) / n
+    sigma = delta / 3
+    amp = _amp_for(orc, n, delta, kind, sigma, xi)
+    md = nlch.make_model(n, delta, kind, amp, sigma, c_F=1.0, beta1=1.0, beta2=0.05, tau=0.01)
+    u = _rand(n, 7 + n, prec)
+    x = torch.from_numpy(u.reshape(-1)).to(TDT[prec]).to(DEV)
+    y = torch.empty_like(x)
+    ooi = torch.zeros(2, dtype=torch.float64, device=DEV)
+    nlch.nlch_step(md, nlch.PRECISIONS[prec], nlch.NLCH_ALGO_AUTO, x, y, ooi)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy().reshape(n, n)
+    ref, _, _ = b2.step_b2(u, n, delta, kind, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+    assert np.max(np.abs(got - ref)) <= TOL[prec]
+    assert np.all(np.abs(got) <= 1)
+    mean = got.mean()
+    assert abs(ooi.cpu().numpy()[1] - 0.5 * (1 + mean)) <= 1e-12
+    if prec == "f64":
+        mu = b2.multiplier(got, u, n, delta, kind, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+        inner = np.abs(got) < 1
+        assert np.max(np.abs(mu[inner])) <= 1e-7
+        assert np.min(mu[got == 1], initial=0.0) >= -1e-7
+        assert np.max(mu[got == -1], initial=0.0) <= 1e-7
+
+
+def _paper_workload(n, nsteps, prec, count=2, c_F=1.0):
+    """The paper's kernel (delta = delta_hf = 0.25, eps^2 = 0.00178),
+    beta1 = 1, beta2 = 0.05, tau = 0.01, four-nuclei data."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    m = synth.Model(n, 0.25, 1, amp, sigma, c_F=c_F, beta1=1.0, beta2=0.05, tau=0.01)
+    smp = [synth.Sample(0, c_F, amp, "nuclei", 6, s, synth.draw_theta(synth.rng_for(6, s)))
+           for s in range(count)]
+    return synth.Workload("b2", [m], smp, nsteps, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_b2_trajectory_paper_parameters(orc, prec):
+    """20 steps at the paper's parameters on 32^2 (delta = 8h): OoI and
+    states against the oracle's trajectory, and the energy trace."""
+    w = _paper_workload(32, 20, prec)
+    m = w.models[0]
+    b = DeviceBatch(w, prec)
+    e = b.solve_energy(nlch.NLCH_ALGO_AUTO)
+    torch.cuda.synchronize()
+    E = e.cpu().numpy()
+    o = b.ooi_host()
+    for i, s in enumerate(w.samples):
+        u0 = rounded_initial(w, s, prec)
+        ref, mean, f1 = b2.solve_b2(u0, w.nsteps, m.n, m.delta, m.kernel, s.amp, m.sigma,
+                                    s.c_F, m.beta1, m.beta2, m.tau)
+        rel = 1e-10 if prec == "f64" else 1e-6
+        assert abs(o[i, 1] - f1) <= rel * abs(f1), (i, o[i, 1], f1)
+        assert np.max(np.abs(b.sample_state(i) - ref)) <= (1e-8 if prec == "f64" else 1e-4)
+        e0 = orc.energy(np.clip(u0, -1, 1), m.n, m.delta, m.kernel, s.amp, m.sigma, s.c_F)
+        eK = orc.energy(b.sample_state(i), m.n, m.delta, m.kernel, s.amp, m.sigma, s.c_F)
+        assert abs(E[0, i] - e0) <= 1e-11 * abs(e0)
+        assert abs(E[-1, i] - eK) <= 1e-11 * abs(eK)
+
+
+def test_b2_mixed_batch_and_resume(orc):
+    """A beta2 > 0 group next to a beta2 = 0 group in one call; each sample
+    equals its own single-sample solve, and a solve split in two calls equals
+    one call (each step starts Newton from the state alone)."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    models = [synth.Model(32, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01),
+              synth.Model(48, 0.125, 1, amp, sigma, beta2=0.0, tau=0.01)]
+    smp = [synth.Sample(k % 2, 1.0, amp, "nuclei", 6, k, synth.draw_theta(synth.rng_for(6, k)))
+           for k in range(4)]
+    w = synth.Workload("mixed_b2", models, smp, 12, "f64")
+    a = DeviceBatch(w)
+    a.solve()
+    c = DeviceBatch(w)
+    c.solve(nsteps=5)
+    c.solve(nsteps=7)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state, c.state)
+    for k in range(4):
+        wk = synth.Workload("one", models, [smp[k]], 12, "f64")
+        bk = DeviceBatch(wk)
+        bk.solve()
+        torch.cuda.synchronize()
+        assert np.array_equal(bk.sample_state(0), a.sample_state(k))
+    m = models[1]
+    _, _, f1 = orc.solve(rounded_initial(w, smp[1], "f64"), 12, m.n, m.delta, m.kernel, amp,
+                         m.sigma, 1.0, 1.0, 0.01)
+    assert abs(a.ooi_host()[1, 1] - f1) <= 1e-12 * f1
+
+
+def test_b2_rejects_nonconvex_steps():
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    # delta < delta_hf truncates the kernel: xi_h < 0
+    w = synth.Workload("nc", [synth.Model(32, 0.125, 1, amp, sigma, beta2=0.05, tau=0.01)],
+                       [synth.Sample(0, 1.0, amp, "iid", 1, 0)], 3, "f64")
+    b = DeviceBatch(w)
+    before = b.state.clone()
+    with pytest.raises(nlch.NlchError) as e:
+        b.solve()
+    assert e.value.code == nlch.NLCH_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert torch.equal(before, b.state)
