@@ -229,8 +229,272 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
         uo[i] = to_store<TS>(ok ? clampd(Z[i] / xi) : nan);
 }
 
+// On-chip variant for n = 64, 88, 128: the same iteration, with the conjugate-
+// gradient loop -- all but a few passes of a step -- kept on the compute
+// unit.  512 threads own up to 32 sites each (site t + 512 k); the CG
+// residual (FP64) and solution (FP32) live in registers, the CG direction
+// (FP64; the only vector read at neighbouring sites) in LDS, and the
+// inactive-set mask in a register bitmask.  z, r, F and the Newton direction stay in the
+// global workspace, touched a few times per Newton step.  The Newton level
+// (F, convergence test, line search, z) is the same FP64 arithmetic as in
+// k_b2_step; only the inner directions differ by rounding.
+constexpr int kB2LdsThreads = 512;
+constexpr int kB2LdsWaves = kB2LdsThreads / 64;
+constexpr int kB2Spt = 32;  // sites per thread: n^2 <= 32 * 512
+
+template <int K>
+__device__ __forceinline__ void block_sums_lds(double (&v)[K], double *red) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < kB2LdsWaves; ++i) s += red[i * K + k];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ double sum1_lds(double v, double *red) {
+    double a[1] = {v};
+    block_sums_lds<1>(a, red);
+    return a[0];
+}
+
+template <class TS, bool GAUSS, int NN>
+__global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
+    const TS *__restrict__ in, TS *__restrict__ out, double *__restrict__ ws,
+    double *__restrict__ epart) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *Pl = reinterpret_cast<double *>(smem_raw);  // CG direction, (n+2)^2
+    __shared__ double red[kB2LdsWaves * 4];
+    const int j = blockIdx.x;
+    const SampleDesc d = sd[ids[j]];
+    // the lattice size is a compile-time constant, so that the stencil's
+    // LDS offsets are instruction immediates rather than registers
+    constexpr int n = NN;
+    constexpr int nn = NN * NN;
+    const int m = geo->m;
+    const TS *u = in + d.offset;
+    TS *uo = out + d.offset;
+    double *R = ws + (int64_t)j * 7 * nn;
+    double *Z = R + nn;
+    double *F = Z + nn;
+    double *X = F + nn;  // Newton direction (for the line search)
+    double *G = X + nn;  // g
+    const double xi = d.xi;
+    const double tb1 = geo->tau_b1, tb2n2 = geo->tau_b2 * (double)nn;
+    const double gs = 2.0 * d.e_int * (double)nn;
+    const double *e = ewd + geo->e_off;
+    const int tid = threadIdx.x;
+
+    // g and the energy partials of u_old
+    double e_ul = 0.0, e_pot = 0.0;
+    for (int i = tid; i < nn; i += kB2LdsThreads) {
+        const int y = i / n, x = i - y * n;
+        const double ui = (double)u[i];
+        double acc = 0.0, lsum = 0.0;
+        for (int dy = -m; dy <= m; ++dy) {
+            const int ady = dy < 0 ? -dy : dy;
+            const int w = geo->halfw[ady];
+            const TS *row = u + (int64_t)wrap_once(y + dy, n) * n;
+            for (int dx = -w; dx <= w; ++dx) {
+                const double v = (double)row[wrap_once(x + dx, n)];
+                const double wt = GAUSS ? e[ady * (m + 1) + (dx < 0 ? -dx : dx)] : 1.0;
+                acc += wt * v;
+                lsum += wt * (ui - v);
+            }
+        }
+        G[i] = gs * acc;
+        e_ul += ui * lsum;
+        e_pot += 1.0 - ui * ui;
+    }
+    if (epart) {
+        double v[2] = {e_ul, e_pot};
+        block_sums_lds<2>(v, red);
+        if (tid == 0) {
+            epart[2 * (int64_t)j] = v[0];
+            epart[2 * (int64_t)j + 1] = v[1];
+        }
+    }
+    __syncthreads();
+    double rr = 0.0;
+    for (int i = tid; i < nn; i += kB2LdsThreads) {
+        const int y = i / n, x = i - y * n;
+        const double ui = (double)u[i];
+        const double r = ui + tau_a(G, i, y, x, n, nn, tb1, tb2n2);
+        R[i] = r;
+        Z[i] = xi * ui;
+        rr += r * r;
+    }
+    const double scale = fmax(1.0, sqrt(sum1_lds(rr, red)));
+
+    // Sites of this thread (t + 512 k, k < SPT) and their places in the LDS
+    // copy of the CG direction, which carries a one-cell periodic halo
+    // ((n+2)^2, row W): the 5-point stencil then needs no wrap-around, and a
+    // boundary site writes its value to the halo cell opposite as well.
+    constexpr int W = n + 2;
+    constexpr int SPT = (nn + kB2LdsThreads - 1) / kB2LdsThreads;
+    static_assert(SPT <= kB2Spt, "sites per thread");
+    auto pad = [](int i) { return i + 2 * (i / n) + n + 3; };  // (y+1) W + x + 1
+    auto put = [&](int i, double v) {
+        const int q = pad(i);
+        const int y = i / n, x = i - y * n;
+        Pl[q] = v;
+        if (x == 0) Pl[q + n] = v;
+        if (x == n - 1) Pl[q - n] = v;
+        if (y == 0) Pl[q + n * W] = v;
+        if (y == n - 1) Pl[q - n * W] = v;
+    };
+
+    bool ok = false;
+    for (int it = 0;; ++it) {
+        // F(z), the CG start (direction -F, to LDS) and the inactive-set mask
+        double f2 = 0.0;
+        unsigned mask = 0;  // bit k: site t + 512 k inactive (|z| < xi)
+#pragma unroll 1
+        for (int k = 0; k < SPT; ++k) {
+            const int i = tid + kB2LdsThreads * k;
+            if (i < nn) {
+                const int y = i / n, x = i - y * n;
+                const double zi = Z[i];
+                const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(zi / xi) - R[i];
+                F[i] = f;
+                put(i, -f);
+                if (fabs(zi) < xi) mask |= 1u << k;
+                f2 += f * f;
+            }
+        }
+        f2 = sum1_lds(f2, red);  // also makes Pl visible
+        if (sqrt(f2) <= 1e-13 * scale) {
+            ok = true;
+            break;
+        }
+        if (it == kMaxNewton) break;
+        // the CG residual in FP64, the direction's running sum in FP32 (a
+        // Newton direction needs ~1e-7 relative accuracy at most: inexact
+        // Newton then still gains 7 digits a step)
+        const double inv_xi = 1.0 / xi;
+        double Sr[SPT];
+        float Xr[SPT];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int i = tid + kB2LdsThreads * k;
+            Sr[k] = i < nn ? Pl[pad(i)] : 0.0;
+            Xr[k] = 0.0f;
+        }
+        // J p at site i from the LDS direction (evaluated twice per
+        // iteration, for p.Jp and for the residual update, instead of being
+        // kept in registers)
+        auto jp = [&](int i, int k) {
+            const int q = pad(i);
+            const double pi = Pl[q];
+            const double ap =
+                tb1 * pi - tb2n2 * (Pl[q + 1] + Pl[q - 1] + Pl[q + W] + Pl[q - W] - 4.0 * pi);
+            return ap + ((mask >> k) & 1u ? pi * inv_xi : 0.0);
+        };
+        const double eta = fmin(1e-2, sqrt(f2) / scale);
+        const double stop = eta * eta * f2;
+        double rs = f2;
+        for (int kk = 0; kk < kMaxCg && rs > stop; ++kk) {
+            double pq = 0.0;
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int i = tid + kB2LdsThreads * k;
+                if (i < nn) pq += Pl[pad(i)] * jp(i, k);
+            }
+            pq = sum1_lds(pq, red);
+            if (!(pq > 0.0)) break;
+            const double alpha = rs / pq;
+            double rn = 0.0;
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int i = tid + kB2LdsThreads * k;
+                if (i < nn) {
+                    Xr[k] = (float)((double)Xr[k] + alpha * Pl[pad(i)]);
+                    Sr[k] -= alpha * jp(i, k);
+                    rn += Sr[k] * Sr[k];
+                }
+            }
+            rn = sum1_lds(rn, red);  // every thread has read Pl before it changes
+            const double beta = rn / rs;
+            rs = rn;
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int i = tid + kB2LdsThreads * k;
+                if (i < nn) put(i, Sr[k] + beta * Pl[pad(i)]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int i = tid + kB2LdsThreads * k;
+            if (i < nn) X[i] = (double)Xr[k];
+        }
+        __syncthreads();
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = tid; i < nn; i += kB2LdsThreads) {
+            const int y = i / n, x = i - y * n;
+            const double taz = F[i] - clampd(Z[i] / xi) + R[i];
+            const double tax = tau_a(X, i, y, x, n, nn, tb1, tb2n2);
+            sm[0] += X[i] * taz;
+            sm[1] += X[i] * tax;
+            sm[2] += R[i] * X[i];
+            sm[3] += F[i] * X[i];
+        }
+        block_sums_lds<4>(sm, red);
+        double a = 1.0;
+        for (int h = 0; h < kMaxHalvings; ++h) {
+            double dp = 0.0;
+            for (int i = tid; i < nn; i += kB2LdsThreads)
+                dp += phi(Z[i] + a * X[i], xi) - phi(Z[i], xi);
+            dp = sum1_lds(dp, red);
+            if (a * sm[0] + 0.5 * a * a * sm[1] + dp - a * sm[2] <= 1e-4 * a * sm[3]) break;
+            a *= 0.5;
+        }
+        for (int i = tid; i < nn; i += kB2LdsThreads) Z[i] += a * X[i];
+        __syncthreads();
+    }
+    const double nan = __builtin_nan("");
+    for (int i = tid; i < nn; i += kB2LdsThreads)
+        uo[i] = to_store<TS>(ok ? clampd(Z[i] / xi) : nan);
+}
+
 template <class TS>
 hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, double *epart) {
+    // on-chip variant for the lattices of the multifidelity study
+    auto lds_launch = [&](auto f, int n) {
+        const size_t lds = sizeof(double) * (size_t)(n + 2) * (n + 2);
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(159 * 1024)) != hipSuccess)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(kB2LdsThreads), lds, s, g.sd, g.ids,
+                           g.geo, g.ewd, (const TS *)in, (TS *)out, g.ws, epart);
+        return hipGetLastError();
+    };
+    const bool gauss = g.kernel == 1;
+    switch (g.n) {
+        case 64:
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, 64>, 64)
+                         : lds_launch(k_b2_step_lds<TS, false, 64>, 64);
+        case 88:
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, 88>, 88)
+                         : lds_launch(k_b2_step_lds<TS, false, 88>, 88);
+        case 128:
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, 128>, 128)
+                         : lds_launch(k_b2_step_lds<TS, false, 128>, 128);
+        default:
+            break;
+    }
     dim3 grid((unsigned)g.nids), block(kB2Threads);
     if (g.kernel == 1)
         hipLaunchKernelGGL((k_b2_step<TS, true>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,

@@ -33,7 +33,9 @@ def _rand(n, seed, prec):
 
 
 CASES = [(16, 4, 0, 0.05), (24, 9, 1, 0.03), (40, 16, 1, 0.08), (64, 64, 0, 0.0253),
-         (50, 25, 1, 0.02), (96, 64, 1, 0.0253)]
+         (50, 25, 1, 0.02), (96, 64, 1, 0.0253),
+         # lattices with the on-chip (LDS) variant
+         (88, 121, 1, 0.0253), (128, 256, 1, 0.0253), (64, 9, 1, 0.1)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
