@@ -137,7 +137,7 @@ def main():
     t0 = time.time()
     host = np.empty(total, dtype=ndt)
     for i, s in enumerate(w.samples):
-        n = w.models[s.model].n
+        n = synth.state_side(w.models[s.model])
         off = samples[i].offset
         host[off:off + n * n] = synth.initial_state(w, s).astype(ndt).reshape(-1)
     init = torch.from_numpy(host).to(dev)
@@ -192,7 +192,8 @@ def main():
     # Dominant kernel: with every sample LDS-resident the solve is one launch.
     m0 = w.models[0]
     R2, mdisc, N, _ = nlch.nlch_disc(m0.n, m0.delta)
-    resident = all(mm.n in (64, 128) for mm in w.models) and (args.algo & 0xff) in (0, 3)
+    resident = all(mm.n in (64, 128) and not mm.boundary for mm in w.models) and \
+        (args.algo & 0xff) in (0, 3)
     kname = "k_resident" if resident else "k_rowrun"
     ops = sum(algorithmic_ops(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
                               w.models[s.model].kernel) * w.models[s.model].n ** 2
@@ -253,11 +254,13 @@ def main():
         import oracle
         o = ooi.view(-1, 2).cpu().numpy()
         rel, tcpu, sscpu, k = [], 0.0, 0, 0
+        cores = oracle.threads()
         cap = min(args.cpu_samples, S)
-        # chunks of 16 consecutive samples (all steps each) until the time
+        chunk = 4 if any(mm.boundary for mm in w.models) else 16
+        # chunks of consecutive samples (all steps each) until the time
         # budget is spent; the sample count is reported
         while k < cap and tcpu < args.cpu_seconds:
-            idx = list(range(k, min(k + 16, cap)))
+            idx = list(range(k, min(k + chunk, cap)))
             by_model = {}
             for i in idx:
                 by_model.setdefault(w.samples[i].model, []).append(i)
@@ -266,24 +269,32 @@ def main():
                 u0 = np.stack([synth.initial_state(w, w.samples[i]).astype(ndt)
                                .astype(np.float64) for i in ids])
                 t = time.perf_counter()
-                _, _, f1 = oracle.solve_many(u0, w.nsteps, mm.n, mm.delta, mm.kernel,
-                                             mm.sigma, mm.beta1, mm.tau,
-                                             [w.samples[i].c_F for i in ids],
-                                             [w.samples[i].amp for i in ids],
-                                             want_states=False)
+                if mm.boundary:
+                    # the bounded-domain oracle (numpy, one thread)
+                    from oracle import volume
+                    f1 = [volume.solve(u0[j], w.nsteps, mm.n, mm.delta, mm.kernel,
+                                       w.samples[i].amp, mm.sigma, w.samples[i].c_F,
+                                       mm.beta1, mm.tau)[2] for j, i in enumerate(ids)]
+                    cores = 1
+                else:
+                    _, _, f1 = oracle.solve_many(u0, w.nsteps, mm.n, mm.delta, mm.kernel,
+                                                 mm.sigma, mm.beta1, mm.tau,
+                                                 [w.samples[i].c_F for i in ids],
+                                                 [w.samples[i].amp for i in ids],
+                                                 want_states=False)
                 tcpu += time.perf_counter() - t
                 sscpu += len(ids) * mm.n ** 2 * w.nsteps
                 for j, i in enumerate(ids):
                     rel.append(abs(o[i, 1] - f1[j]) / abs(f1[j]))
             k = idx[-1] + 1
         out["cpu_baseline"] = {"value": sscpu / tcpu, "unit": "site-steps/s",
-                               "cores": oracle.threads(), "kind": "oracle",
+                               "cores": cores, "kind": "oracle",
                                "sample": "samples 0..%d of %d, all %d steps each "
                                          "(%.1f s of oracle time)"
                                          % (k - 1, S, w.nsteps, tcpu)}
         out["ooi_rel_err"] = {"max": max(rel), "samples": k, "vs": "FP64 CPU oracle"}
         log("cpu oracle %.3e site-steps/s on %d threads; max OoI rel err %.2e"
-            % (sscpu / tcpu, oracle.threads(), max(rel)))
+            % (sscpu / tcpu, cores, max(rel)))
 
     print(json.dumps(out), flush=True)
 

@@ -34,6 +34,23 @@
  * within its iteration cap gets a NaN state and output of interest.
  * Per sample the library keeps 7 n^2 doubles of workspace with the batch.
  *
+ * Bounded domain (NLCH_BOUNDARY_VOLUME; Sec. 2.1: the operator integrates
+ * over Omega = (0,1)^2 together with the interaction region Omega_I of points
+ * outside Omega within delta of it).  The paper does not state the values
+ * imposed on Omega_I; this library reads them as a volume constraint: u on
+ * Omega_I is data that the evolution keeps fixed.  Omega's lattice is n x n
+ * (h = 1/n) and is continued by m = floor(sqrt(R2)) nodes on every side,
+ * which holds every node of Omega_I a disc centred in Omega reaches.  A
+ * sample's state is then the (n + 2m) x (n + 2m) array (row-major, element
+ * (y, x) at y*(n + 2m) + x) whose inner n x n block, rows and columns
+ * m .. m + n - 1, is Omega and whose ring of width m holds the Omega_I data.
+ * Every disc centred in Omega lies in Omega and Omega_I, so c_gamma_h, xi_h
+ * and the update are those of the torus; only Omega's nodes are updated, the
+ * ring is copied (after the initial projection onto [-1, 1], which covers
+ * every node), and the output of interest is the mean over Omega's n^2
+ * nodes.  This mode needs beta2 = 0 and is built for the DIRECT and ROWRUN
+ * algorithms without the energy trace.
+ *
  * Conventions for every entry point:
  *  - Status: 0 on success, else one of the NLCH_E* codes; the message of the
  *    last failure on the calling thread is returned by nlch_last_error().
@@ -100,6 +117,11 @@ extern "C" {
                                     this flag the shape is a fixed function
                                     of the batch, so results repeat exactly. */
 
+/* Domain of a model. */
+#define NLCH_BOUNDARY_PERIODIC 0 /* periodic unit square, state n x n          */
+#define NLCH_BOUNDARY_VOLUME 1   /* Omega = (0,1)^2 with fixed values on
+                                    Omega_I, state (n + 2m) x (n + 2m)         */
+
 /* One fidelity level ("model"): lattice, horizon, kernel and evolution
  * parameters (Sec. 2.1 and Sec. 4). */
 typedef struct nlch_model {
@@ -112,11 +134,14 @@ typedef struct nlch_model {
     double beta1;        /* > 0                                                 */
     double beta2;        /* >= 0; > 0 needs n <= 256 and xi_h > 0 per sample   */
     double tau;          /* time step > 0 with 1 + tau beta1 xi_h > 0           */
+    int32_t boundary;    /* NLCH_BOUNDARY_*                                     */
+    int32_t reserved;    /* must be 0                                           */
 } nlch_model;
 
 /* One sampled input of a batch: its model, its own c_F and kernel amplitude
- * (the random parameters of Sec. 4), and the element offset of its n x n
- * state inside the batch buffers. */
+ * (the random parameters of Sec. 4), and the element offset of its state
+ * (n x n elements, (n + 2m) x (n + 2m) under NLCH_BOUNDARY_VOLUME) inside the
+ * batch buffers. */
 typedef struct nlch_sample {
     int32_t model;      /* index into the models array                          */
     int32_t reserved;   /* must be 0                                            */
@@ -158,7 +183,10 @@ int nlch_model_constants(const nlch_model *model, double *c_gamma_h,
  * receives {mean(u_out), f_1(u_out)} (eq. ooi).  algo: NLCH_ALGO_DIRECT or
  * NLCH_ALGO_ROWRUN (AUTO picks one), optionally | NLCH_ALGO_ACC64.  No initial
  * projection: u_in is used as given.  Exactly one launch of the step kernel
- * (plus one reduction launch if ooi_out != NULL). */
+ * (plus one reduction launch if ooi_out != NULL).  NLCH_BOUNDARY_VOLUME:
+ * u_in and u_out hold (n + 2m)^2 elements; the ring of u_out receives the
+ * ring of u_in projected onto [-1, 1] (one more elementwise launch before the
+ * step). */
 int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
               const void *u_in, void *u_out, double *ooi_out, void *hip_stream);
 
@@ -167,10 +195,11 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
  * model, c_F and amplitude, then u^nsteps is left in state_s and
  * {mean, f_1} in ooi_out[2s], ooi_out[2s+1] (FP64).
  * models: n_models >= 1 host structs; samples: n_samples >= 1 host structs.
- * state: device buffer holding every sample's n*n elements at its offset
+ * state: device buffer holding every sample's state at its offset
  * (in: u0, out: final state).  scratch: device buffer of the same extent,
  * used as the ping-pong partner (may be NULL when every sample runs
- * RESIDENT).  ooi_out: device array of 2*n_samples doubles.
+ * RESIDENT; under NLCH_BOUNDARY_VOLUME the projected ring is written to both
+ * buffers).  ooi_out: device array of 2*n_samples doubles.
  * Samples of different models (uneven n and horizon) may be mixed; the
  * library never reorders outputs.  Without NLCH_ALGO_NOGRAPH the sequence of
  * launches is captured once into a HIP graph per distinct call signature
@@ -197,7 +226,8 @@ int nlch_solve_batch(const nlch_model *models, int32_t n_models,
  * evaluation per sample for k = nsteps (whose update goes to `scratch`, whose
  * contents are unspecified afterwards) and, for the streaming kernels, one
  * small reduction launch per step.  All other arguments, results and errors
- * are those of nlch_solve_batch; energy_out == NULL is NLCH_EINVAL. */
+ * are those of nlch_solve_batch; energy_out == NULL is NLCH_EINVAL, and a
+ * model with NLCH_BOUNDARY_VOLUME is NLCH_EUNSUPPORTED. */
 int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
                             const nlch_sample *samples, int64_t n_samples,
                             int32_t nsteps, int32_t precision, int32_t algo,

@@ -70,6 +70,24 @@ def step(U, n, delta, kind, amp, sigma, c_F, beta1, tau):
     return out
 
 
+def step_sites(U, sites, n, delta, kind, amp, sigma, c_F, beta1, tau):
+    """One step evaluated only at the listed nodes of Omega (flat indices
+    y n + x of Omega's n x n lattice), for large lattices."""
+    ddy, ddx, wd, c_gamma = weights(n, delta, kind, amp, sigma)
+    m = ring_width(n, delta)
+    den = 1.0 + tau * beta1 * (c_gamma - c_F)
+    if not den > 0.0:
+        raise ValueError("1 + tau beta1 xi_h must be > 0")
+    U = np.asarray(U, dtype=np.float64)
+    sites = np.asarray(sites, dtype=np.int64)
+    y = sites // n + m
+    x = sites % n + m
+    g = np.zeros(sites.size)
+    for dy, dx, w in zip(ddy, ddx, wd):
+        g += w * U[y + dy, x + dx]
+    return np.clip((U[y, x] + tau * beta1 * g) / den, -1.0, 1.0)
+
+
 def ooi(U, n, m):
     """(mean over Omega, f_1 = (1 + mean) / 2)."""
     inner = np.asarray(U, dtype=np.float64)[m:m + n, m:m + n]

@@ -509,7 +509,7 @@ hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, do
 
 hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, hipStream_t s,
                           double *epart) {
-    if (!g.ws || g.n > kB2MaxN) return hipErrorInvalidValue;
+    if (!g.ws || g.n > kB2MaxN || g.lo != 0) return hipErrorInvalidValue;
     switch (prec) {
         case kF64: return b2_typed<double>(g, in, out, s, epart);
         case kF32: return b2_typed<float>(g, in, out, s, epart);

@@ -60,11 +60,15 @@ __global__ __launch_bounds__(kElemThreads) void k_count_nonfinite(
 }
 
 // Output of interest, pass 1: FP64 partial sums of fixed chunks of every
-// sample's state (one workgroup per chunk).
+// sample's state (one workgroup per chunk).  The sum runs over the ni x ni
+// block that starts at row and column `ring` of the side x side array: the
+// whole state on the torus (ring = 0, ni = side), the lattice of Omega
+// without the fixed ring under a volume constraint.
 template <class TS>
 __global__ __launch_bounds__(256) void k_ooi_partial(const SampleDesc *__restrict__ sd,
                                                      const int32_t *__restrict__ ids,
-                                                     int64_t nn, int chunks,
+                                                     int64_t nn, int chunks, int ni,
+                                                     int side, int ring,
                                                      const TS *__restrict__ st,
                                                      double *__restrict__ partial) {
     __shared__ double red[4];
@@ -74,7 +78,14 @@ __global__ __launch_bounds__(256) void k_ooi_partial(const SampleDesc *__restric
     const int64_t hi = lo + kOoiChunk < nn ? lo + kOoiChunk : nn;
     const TS *s = st + d.offset;
     double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += (double)s[i];
+    if (ring == 0) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += (double)s[i];
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+            const int64_t y = i / ni, x = i - y * ni;
+            acc += (double)s[(y + ring) * side + x + ring];
+        }
+    }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) partial[b] = tot;
 }
@@ -107,10 +118,11 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(
     __shared__ double red[kDirThreads / 64];
     TA *tile = reinterpret_cast<TA *>(smem_raw);
     const int n = geo->n, m = geo->m;
+    const int ne = n - geo->lo;  // updated block [lo, ne)^2 (see ModelGeo)
     const int b = xcd_remap(blockIdx.x, nblocks);
     const SampleDesc d = sd[ids[b / tiles_per_sample]];
     const int t = b % tiles_per_sample;
-    const int x0 = (t % tiles_x) * kDirTX, y0 = (t / tiles_x) * kDirTY;
+    const int x0 = geo->lo + (t % tiles_x) * kDirTX, y0 = geo->lo + (t / tiles_x) * kDirTY;
     const TS *src = in + d.offset;
     TS *dst = out + d.offset;
     const int W = kDirTX + 2 * m, H = kDirTY + 2 * m;
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(
                 }
             }
         }
-        if (y < n && x < n) {
+        if (y < ne && x < ne) {
             dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(uc, acc, a, bb));
             e_ul += (double)uc * (double)acc;
             e_pot += 1.0 - (double)uc * (double)uc;
@@ -245,21 +257,21 @@ int ooi_chunks(int n) { return (int)(((int64_t)n * n + kOoiChunk - 1) / kOoiChun
 
 hipError_t launch_ooi(int prec, const Group &g, const void *state, double *ooi, int,
                       hipStream_t s) {
-    const int64_t nn = (int64_t)g.n * g.n;
-    const int ch = ooi_chunks(g.n);
+    const int64_t nn = (int64_t)g.ni * g.ni;
+    const int ch = ooi_chunks(g.ni);
     dim3 grid((unsigned)(ch * g.nids)), block(256);
     switch (prec) {
         case kF64:
             hipLaunchKernelGGL((k_ooi_partial<double>), grid, block, 0, s, g.sd, g.ids, nn, ch,
-                               (const double *)state, g.partial);
+                               g.ni, g.n, g.lo, (const double *)state, g.partial);
             break;
         case kF32:
             hipLaunchKernelGGL((k_ooi_partial<float>), grid, block, 0, s, g.sd, g.ids, nn, ch,
-                               (const float *)state, g.partial);
+                               g.ni, g.n, g.lo, (const float *)state, g.partial);
             break;
         default:
             hipLaunchKernelGGL((k_ooi_partial<half_t>), grid, block, 0, s, g.sd, g.ids, nn, ch,
-                               (const half_t *)state, g.partial);
+                               g.ni, g.n, g.lo, (const half_t *)state, g.partial);
             break;
     }
     hipLaunchKernelGGL(k_ooi_final, dim3((unsigned)g.nids), dim3(64), 0, s, g.ids, nn, ch,
@@ -277,8 +289,8 @@ const double *ew_for<double>(const Group &g) { return g.ewd; }
 template <class TS, class TA>
 static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStream_t s,
                                double *epart) {
-    const int tiles_x = (g.n + kDirTX - 1) / kDirTX;
-    const int tiles_y = (g.n + kDirTY - 1) / kDirTY;
+    const int tiles_x = (g.ni + kDirTX - 1) / kDirTX;
+    const int tiles_y = (g.ni + kDirTY - 1) / kDirTY;
     const int tps = tiles_x * tiles_y;
     const int64_t nb = (int64_t)tps * g.nids;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;

@@ -35,8 +35,8 @@ hipError_t stream_launch(const Group &g, const StreamShape &sh, const void *in, 
                          hipStream_t s, double *epart) {
     constexpr int TX = 64 * R;
     constexpr int P = Disc<R2>::P;
-    const int strips = (g.n + TX - 1) / TX;
-    const int bands = (g.n + sh.B - 1) / sh.B;
+    const int strips = (g.ni + TX - 1) / TX;
+    const int bands = (g.ni + sh.B - 1) / sh.B;
     const int64_t nb = (int64_t)strips * bands * g.nids;
     if (nb > 0x7fffffff || sh.B < 1 || sh.W < 1 || sh.W > 8) return hipErrorInvalidValue;
     if (sh.W == 1) {
@@ -82,7 +82,8 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
     constexpr int M = Disc<R2>::M;
     const int threads = 64 * (g.n / kResB);
     const size_t lds = resident_lds_bytes(g.n, M, kResB, sizeof(TS), sizeof(TA));
-    if ((g.n != 64 && g.n != 128) || lds > kLdsBytes - 1024) return hipErrorInvalidValue;
+    if ((g.n != 64 && g.n != 128) || g.lo != 0 || lds > kLdsBytes - 1024)
+        return hipErrorInvalidValue;
     auto go = [&](auto f) {
         // per kernel (every instantiation has the same pointer type, so no
         // per-type static flag here)

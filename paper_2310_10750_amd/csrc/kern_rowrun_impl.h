@@ -150,17 +150,20 @@ __global__ __launch_bounds__(64) void k_stream(
     __shared__ __align__(16) TA ring[2][64 * CPL];
 
     const int n = geo->n;
+    // updated block: rows and columns [lo, ne) (the whole lattice on the
+    // torus; without the ring of fixed values under a volume constraint)
+    const int lo = geo->lo, ne = n - geo->lo;
     const int bidx = xcd_remap(blockIdx.x, nblocks);
     const int per_sample = strips * bands;
     const SampleDesc d = sd[ids[bidx / per_sample]];
     const int t = bidx % per_sample;
-    const int x0 = (t % strips) * TX;
-    const int y0 = (t / strips) * B;
+    const int x0 = lo + (t % strips) * TX;
+    const int y0 = lo + (t / strips) * B;
     const TS *src = in + d.offset;
     TS *dst = out + d.offset;
     const int lane = threadIdx.x;
     const int c0 = lane * R;
-    const int bq = y0 + B <= n ? B : n - y0;  // output rows of this band
+    const int bq = y0 + B <= ne ? B : ne - y0;  // output rows of this band
     const int rows = bq + 2 * M;
 
     // wrapped source columns of this lane's staged elements; lanes past the
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(64) void k_stream(
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int x = x0 + c0 + c;
-        xcl[c] = x < n ? x : 0;
+        xcl[c] = x < ne ? x : 0;
         cnext[c] = src[(int64_t)y0 * n + xcl[c]];
     }
 
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(64) void k_stream(
                         const int x = x0 + c0 + c;
                         const TA u = to_acc<TA>(cen[c]);
                         const TA lsum = ce * u - acc[done][c];
-                        if (x < n) {
+                        if (x < ne) {
                             dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
                             if (epart) {
                                 e_ul += u * lsum;
@@ -331,16 +334,17 @@ __global__ __launch_bounds__(512) void k_band(
     TA *heads = reinterpret_cast<TA *>(smem_raw) + (size_t)W * LD::RING;
 
     const int n = geo->n;
+    const int lo = geo->lo, ne = n - geo->lo;  // updated block [lo, ne)^2
     const int bidx = xcd_remap(blockIdx.x, nblocks);
     const int per_sample = strips * bands;
     const SampleDesc d = sd[ids[bidx / per_sample]];
     const int tile = bidx % per_sample;
-    const int x0 = (tile % strips) * TX;
-    const int y0 = (tile / strips) * BW;
+    const int x0 = lo + (tile % strips) * TX;
+    const int y0 = lo + (tile / strips) * BW;
     const TS *src = in + d.offset;
     TS *dst = out + d.offset;
     const int c0 = lane * R;
-    const int bq = y0 + BW <= n ? BW : n - y0;  // output rows of this band
+    const int bq = y0 + BW <= ne ? BW : ne - y0;  // output rows of this band
     const int T = bq + 2 * M;                    // input rows of this band
     // waves with rows to walk; wave wv walks input rows [s, s + Lw) of the
     // band's T rows and retires outputs q = s + t - 2m (q relative to y0)
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(512) void k_band(
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int x = x0 + c0 + c;
-        xcl[c] = x < n ? x : 0;
+        xcl[c] = x < ne ? x : 0;
     }
 
     TA acc[P][R];
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(512) void k_band(
                             const int x = x0 + c0 + c;
                             const TA u = to_acc<TA>(cen[c]);
                             const TA lsum = ce * u - acc[done][c];
-                            if (x < n) {
+                            if (x < ne) {
                                 dst[(int64_t)y * n + x] =
                                     to_store<TS>(update<TA>(u, lsum, a, bcoef));
                                 if (epart) {
@@ -483,7 +487,7 @@ __global__ __launch_bounds__(512) void k_band(
                                    heads[((size_t)(wv + 1) * 2 * M + k) * TX + c0 + c];
                     const TA u = to_acc<TA>(src[(int64_t)y * n + xcl[c]]);
                     const TA lsum = ce * u - sum;
-                    if (x < n) {
+                    if (x < ne) {
                         dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
                         if (epart) {
                             e_ul += u * lsum;

@@ -119,6 +119,8 @@ static int64_t isqrt64(int64_t v) {
 struct ModelInfo {
     int64_t R2 = 0, N = 0;
     int m = 0;
+    int lo = 0;                  // ring width: m under a volume constraint, else 0
+    int side = 0;                // side of a stored state, n + 2 lo
     std::vector<int32_t> halfw;  // |dy| = 0..m
     double sum_e = 0.0;          // sum_{d in D} e_d, e_d exact 2-D unit weights
     double ce_sep = 0.0;         // sum_{d in D} g(|dy|) g(|dx|)
@@ -147,6 +149,12 @@ static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) 
         return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 is built for n <= %d (one workgroup "
                     "per sample)", what, kB2MaxN);
     if (!finite_pos(md.tau)) return fail(NLCH_EINVAL, "%s: tau must be > 0", what);
+    if (md.boundary != NLCH_BOUNDARY_PERIODIC && md.boundary != NLCH_BOUNDARY_VOLUME)
+        return fail(NLCH_EINVAL, "%s: unknown boundary %d", what, md.boundary);
+    if (md.reserved != 0) return fail(NLCH_EINVAL, "%s: reserved field must be 0", what);
+    if (md.boundary == NLCH_BOUNDARY_VOLUME && md.beta2 > 0.0)
+        return fail(NLCH_EUNSUPPORTED, "%s: the volume-constrained domain is built for "
+                    "beta2 = 0 only", what);
 
     const double r = md.delta * (double)md.n;
     mi.R2 = (int64_t)std::floor(r * r + 1e-9);
@@ -158,6 +166,8 @@ static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) 
         return fail(NLCH_EINVAL, "%s: lattice n = %d must exceed twice the horizon (%d)", what,
                     md.n, mi.m);
     const int m = mi.m;
+    mi.lo = md.boundary == NLCH_BOUNDARY_VOLUME ? m : 0;
+    mi.side = md.n + 2 * mi.lo;
     mi.halfw.resize(m + 1);
     mi.N = 0;
     for (int dy = -m; dy <= m; ++dy) {
@@ -300,7 +310,8 @@ int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nl
         *variant = kB2;
         return NLCH_OK;
     }
-    const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n);
+    const bool res = batch && mi.lo == 0 &&
+                     resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n);
     const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
     switch (base) {
         case NLCH_ALGO_AUTO:
@@ -319,8 +330,9 @@ int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nl
             if (!batch) return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
             if (!res)
                 return fail(NLCH_EUNSUPPORTED,
-                            "RESIDENT needs n <= 128, a sample that fits in LDS and a built "
-                            "R2 (n = %d, R2 = %lld)", md.n, (long long)mi.R2);
+                            "RESIDENT needs the periodic domain, n <= 128, a sample that fits "
+                            "in LDS and a built R2 (n = %d, R2 = %lld)", md.n,
+                            (long long)mi.R2);
             *variant = kResident;
             return NLCH_OK;
         default:
@@ -365,7 +377,8 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     for (int i = 0; i < n_models; ++i) {
         ModelGeo &gm = geo[i];
         std::memset(&gm, 0, sizeof(gm));
-        gm.n = models[i].n;
+        gm.n = mi[i].side;
+        gm.lo = mi[i].lo;
         gm.m = mi[i].m;
         gm.R2 = (int32_t)mi[i].R2;
         gm.N = (int32_t)mi[i].N;
@@ -398,12 +411,12 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         std::memset(&d, 0, sizeof(d));
         d.offset = sm.offset;
         d.model = sm.model;
-        d.n = models[sm.model].n;
+        d.n = mi[sm.model].side;
         d.a = c.a;
         d.b = c.b;
         d.af = rne_f32(c.a);
         d.bf = rne_f32(c.b);
-        const double h2 = 1.0 / ((double)d.n * d.n);
+        const double h2 = 1.0 / ((double)models[sm.model].n * models[sm.model].n);
         d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
         d.e_pot = 0.5 * h2 * sm.c_F;
         d.xi = c.xi_h;
@@ -422,7 +435,9 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         Group g;
         std::memset(&g, 0, sizeof(g));
         g.nids = (int32_t)per_model[i].size();
-        g.n = models[i].n;
+        g.n = mi[i].side;
+        g.lo = mi[i].lo;
+        g.ni = models[i].n;
         g.m = mi[i].m;
         g.R2 = (int32_t)mi[i].R2;
         g.kernel = models[i].kernel;
@@ -450,7 +465,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         part_off[gi] = npart;
         if (b->variant[gi] != kResident)
-            npart += (size_t)ooi_chunks(b->groups[gi].n) * b->groups[gi].nids;
+            npart += (size_t)ooi_chunks(b->groups[gi].ni) * b->groups[gi].nids;
     }
     HIP_TRY(hipMalloc(&b->partial.p, sizeof(double) * npart));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -475,10 +490,10 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
 // waves per band walking L = k (2m+1) rows each (k = 1, 2, 4).  Every
 // candidate is timed over three launches after a warm-up.
 struct TuneKey {
-    int dev, prec, R2, kernel, n, nids;
+    int dev, prec, R2, kernel, n, lo, nids;
     bool operator<(const TuneKey &o) const {
-        return std::tie(dev, prec, R2, kernel, n, nids) <
-               std::tie(o.dev, o.prec, o.R2, o.kernel, o.n, o.nids);
+        return std::tie(dev, prec, R2, kernel, n, lo, nids) <
+               std::tie(o.dev, o.prec, o.R2, o.kernel, o.n, o.lo, o.nids);
     }
 };
 struct TuneVal {
@@ -496,7 +511,7 @@ void set_shape(Group &g, const TuneVal &v) {
 
 int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void *out,
                    hipStream_t s) {
-    const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.nids};
+    const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.lo, g.nids};
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
         set_shape(g, it->second);
@@ -506,17 +521,17 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
     const int bmin = g.m * 2 > 16 ? g.m * 2 : 16;
     std::vector<TuneVal> cands;
     for (int R = 1; R <= 2; ++R) {
-        const int strips = (g.n + 64 * R - 1) / (64 * R);
+        const int strips = (g.ni + 64 * R - 1) / (64 * R);
         for (int B = bmin;; B *= 2) {
-            const int Bc = B < g.n ? B : g.n;
-            const int64_t waves = (int64_t)strips * ((g.n + Bc - 1) / Bc) * g.nids;
-            if (waves >= 128 || Bc == bmin || Bc == g.n) cands.push_back({R, Bc, 1, 0});
-            if (Bc >= g.n) break;
+            const int Bc = B < g.ni ? B : g.ni;
+            const int64_t waves = (int64_t)strips * ((g.ni + Bc - 1) / Bc) * g.nids;
+            if (waves >= 128 || Bc == bmin || Bc == g.ni) cands.push_back({R, Bc, 1, 0});
+            if (Bc >= g.ni) break;
         }
         for (int W = 2; W <= 8 && band_built(g.m, g.ta_bytes); W *= 2)
             for (int k = 1; k <= 4; k *= 2) {
                 const int L = k * P;
-                if (W * L - 2 * g.m > 2 * g.n) continue;  // far more rows than the lattice
+                if (W * L - 2 * g.m > 2 * g.ni) continue;  // far more rows than the lattice
                 cands.push_back({R, 0, W, L});
             }
     }
@@ -583,7 +598,7 @@ int ensure_b2ws(Batch &b) {
 int step_blocks_per_sample(int variant, const Group &g) {
     if (variant == kRowrun) return stream_shape(g).per_sample;
     if (variant == kB2) return 1;
-    return direct_tiles(g.n);
+    return direct_tiles(g.ni);
 }
 
 // Energy partial-sum area of streaming group gi (after ensure_epart).
@@ -632,6 +647,9 @@ int enqueue_group(Batch &b, size_t gi, int prec, bool acc64, int nsteps, void *s
     }
     void *buf0 = (nsteps % 2) ? scratch : state;
     void *buf1 = (buf0 == state) ? scratch : state;
+    // the steps write the updated block only: under a volume constraint both
+    // buffers need the (projected) ring of fixed values
+    if (g.lo != 0 && nsteps > 0) HIP_TRY(launch_project(prec, g, state, buf1, s));
     HIP_TRY(launch_project(prec, g, state, buf0, s));
     double *ep = energy ? group_epart(b, gi) : nullptr;
     const int ps = step_blocks_per_sample(variant, g);
@@ -710,6 +728,9 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         snprintf(what, sizeof(what), "model %d", i);
         rc = analyze_model(models[i], mi[i], what);
         if (rc) return rc;
+        if (energy_out && mi[i].lo != 0)
+            return fail(NLCH_EUNSUPPORTED, "%s: the energy trace is built for the periodic "
+                        "domain only", what);
     }
     // Samples: indices, parameters, non-overlapping states.
     std::vector<std::pair<int64_t, int64_t>> extents((size_t)n_samples);
@@ -723,8 +744,8 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         if (!finite_pos(sm.c_F) || !finite_pos(sm.kernel_amp))
             return fail(NLCH_EINVAL, "sample %lld: c_F and kernel_amp must be > 0", (long long)s);
         if (sm.offset < 0) return fail(NLCH_EINVAL, "sample %lld: negative offset", (long long)s);
-        const int64_t nn = (int64_t)models[sm.model].n * models[sm.model].n;
-        extents[(size_t)s] = {sm.offset, sm.offset + nn};
+        const int64_t side = mi[sm.model].side;
+        extents[(size_t)s] = {sm.offset, sm.offset + side * side};
         Coef c;
         char what[48];
         snprintf(what, sizeof(what), "sample %lld", (long long)s);
@@ -841,7 +862,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
 
 extern "C" {
 
-int nlch_version(void) { return 3; }
+int nlch_version(void) { return 4; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 
@@ -901,7 +922,7 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     ModelInfo mi;
     rc = analyze_model(*model, mi, "model");
     if (rc) return rc;
-    const size_t bytes = prec_size(precision) * (size_t)model->n * model->n;
+    const size_t bytes = prec_size(precision) * (size_t)mi.side * mi.side;
     const char *pi = (const char *)u_in, *po = (const char *)u_out;
     if (pi < po + bytes && po < pi + bytes)
         return fail(NLCH_EINVAL, "u_in and u_out overlap (the stencil reads neighbours)");
@@ -935,6 +956,8 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     rc = ensure_b2ws(*b);
     if (rc) return rc;
     const Group &g = b->groups[0];
+    // the step writes the updated block only; the fixed ring is carried over
+    if (g.lo != 0) HIP_TRY(launch_project(precision, g, u_in, u_out, s));
     HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
     if (ooi_out) HIP_TRY(launch_ooi(precision, g, u_out, ooi_out, 2, s));
     return NLCH_OK;

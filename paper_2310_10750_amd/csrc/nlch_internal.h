@@ -19,9 +19,13 @@ enum Prec { kF64 = 0, kF32 = 1, kF16 = 2 };
 // The exact 2-D unit weights e(|dy|,|dx|) = exp(-h^2 |d|^2 / sigma^2) used by
 // the direct kernel live in a separate table at offset e_off, row-major
 // (m+1) x (m+1).
+// n is the side of a sample's stored array.  The kernels update the block of
+// rows and columns [lo, n - lo): the whole periodic lattice (lo = 0), or,
+// under a volume constraint, the lattice of Omega inside a ring of lo = m
+// rows and columns of fixed values on the interaction region.
 struct ModelGeo {
     int32_t n, m, R2, N;
-    int32_t kernel, pad0;
+    int32_t kernel, lo;
     int64_t e_off;
     double ced;
     double tau_b1, tau_b2;  // tau beta1, tau beta2 (the beta2 > 0 step)
@@ -57,7 +61,8 @@ struct Group {
     double *partial;        // device scratch: ooi_chunks(n) doubles per sample
     double *ws;             // beta2 > 0 groups: b2_ws_doubles(n) doubles per sample
     int32_t nids;
-    int32_t n, m, R2;
+    int32_t n, m, R2;        // n: side of the stored array (as ModelGeo::n)
+    int32_t lo, ni;          // updated block [lo, lo + ni)^2, ni = n - 2 lo
     int32_t kernel;
     int32_t model;
     int32_t tune_R, tune_B;  // streaming shape (0 = heuristic): columns per
@@ -111,7 +116,7 @@ constexpr bool band_built(int M, int ta_bytes) { return ta_bytes == 4 && M <= 16
 
 inline StreamShape stream_shape(const Group &g) {
     StreamShape sh;
-    sh.R = (g.tune_R == 1 || g.tune_R == 2) ? g.tune_R : stream_lanes_cols(g.n, g.m, g.nids);
+    sh.R = (g.tune_R == 1 || g.tune_R == 2) ? g.tune_R : stream_lanes_cols(g.ni, g.m, g.nids);
     sh.W = g.tune_W > 1 && band_built(g.m, g.ta_bytes) ? g.tune_W : 1;
     // fewer waves per band where the partial-sum areas would not fit in LDS
     while (sh.W > 1 && stream_lds_bytes(sh.R, g.m, sh.W, g.ta_bytes) > 159 * 1024) sh.W /= 2;
@@ -120,10 +125,10 @@ inline StreamShape stream_shape(const Group &g) {
         sh.B = sh.W * sh.L - 2 * g.m;
     } else {
         sh.L = 2 * g.m + 1;
-        sh.B = g.tune_B > 0 ? g.tune_B : stream_band_rows(g.n, g.m, 64 * sh.R, g.nids);
+        sh.B = g.tune_B > 0 ? g.tune_B : stream_band_rows(g.ni, g.m, 64 * sh.R, g.nids);
     }
-    if (sh.B > g.n) sh.B = g.n;
-    sh.per_sample = ((g.n + 64 * sh.R - 1) / (64 * sh.R)) * ((g.n + sh.B - 1) / sh.B);
+    if (sh.B > g.ni) sh.B = g.ni;
+    sh.per_sample = ((g.ni + 64 * sh.R - 1) / (64 * sh.R)) * ((g.ni + sh.B - 1) / sh.B);
     return sh;
 }
 

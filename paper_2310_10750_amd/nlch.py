@@ -36,6 +36,9 @@ NLCH_ALGO_NOGRAPH = 0x200
 NLCH_ALGO_CHECK_FINITE = 0x400
 NLCH_ALGO_AUTOTUNE = 0x800
 
+NLCH_BOUNDARY_PERIODIC = 0
+NLCH_BOUNDARY_VOLUME = 1
+
 NLCH_MFMC_MAX_K = 8
 NLCH_MFMC_MAX_POOL = 16
 
@@ -47,7 +50,8 @@ class nlch_model(ctypes.Structure):
                 ("delta", ctypes.c_double), ("kernel_amp", ctypes.c_double),
                 ("kernel_sigma", ctypes.c_double), ("c_F", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
-                ("tau", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("boundary", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class nlch_sample(ctypes.Structure):
@@ -180,9 +184,9 @@ def nlch_disc(n: int, delta: float):
 
 
 def make_model(n, delta, kernel, amp, sigma=0.0, c_F=1.0, beta1=1.0, beta2=0.0,
-               tau=0.01) -> nlch_model:
+               tau=0.01, boundary=0) -> nlch_model:
     return nlch_model(int(n), int(kernel), float(delta), float(amp), float(sigma),
-                      float(c_F), float(beta1), float(beta2), float(tau))
+                      float(c_F), float(beta1), float(beta2), float(tau), int(boundary), 0)
 
 
 def nlch_model_constants(model: nlch_model):
@@ -289,13 +293,14 @@ def mfmc_allocate(subset, cost, rho, budget):
 def structs_for(workload):
     """nlch_model / nlch_sample arrays for a synth.Workload, states packed
     contiguously in sample order.  Returns (models, samples, total_elements)."""
+    from .synth import state_side
     models = (nlch_model * len(workload.models))(*[
         make_model(m.n, m.delta, m.kernel, m.amp, m.sigma, m.c_F, m.beta1, m.beta2,
-                   m.tau) for m in workload.models])
+                   m.tau, getattr(m, "boundary", 0)) for m in workload.models])
     samples = (nlch_sample * len(workload.samples))()
     off = 0
     for i, s in enumerate(workload.samples):
-        n = workload.models[s.model].n
+        side = state_side(workload.models[s.model])
         samples[i] = nlch_sample(s.model, 0, float(s.c_F), float(s.amp), off)
-        off += n * n
+        off += side * side
     return models, samples, off

@@ -54,6 +54,18 @@ class Model:
     beta1: float = 1.0
     beta2: float = 0.0
     tau: float = 0.01
+    boundary: int = 0  # 0: periodic torus; 1: Omega = (0,1)^2, fixed data on Omega_I
+
+
+def state_side(m: Model) -> int:
+    """Side of a sample's stored array: n on the torus, n + 2r with the ring
+    of r = isqrt(floor((delta n)^2 + 1e-9)) lattice rows of Omega_I data under
+    a volume constraint (the layout of the C ABI)."""
+    if not m.boundary:
+        return m.n
+    t = m.delta * m.n
+    r = math.isqrt(int(math.floor(t * t + 1e-9)))
+    return m.n + 2 * r
 
 
 @dataclass(frozen=True)
@@ -148,10 +160,13 @@ def ic_nuclei_batch(n: int, thetas, device="cuda:0"):
 
 
 def initial_state(w: Workload, s: Sample) -> np.ndarray:
-    n = w.models[s.model].n
+    """The sample's stored initial array (state_side x state_side; under a
+    volume constraint its ring is the Omega_I data)."""
+    m = w.models[s.model]
+    n = state_side(m)
     if s.ic == "iid":
         return ic_iid(n, s.seed, s.index)
-    if s.ic == "nuclei":
+    if s.ic == "nuclei" and not m.boundary:
         return ic_nuclei(n, s.theta)
     raise ValueError("unknown initial datum kind %r" % s.ic)
 
@@ -245,6 +260,24 @@ def workload(name: str, n_samples: int = None, nsteps: int = None,
                      "MFMC ensemble: 1024^2 x8, 256^2 x64, 128^2 x512, 64^2 x4096,"
                      " delta=1/32, Gaussian kernel, shared four-nuclei draws, "
                      "100 steps of tau=0.01", list(counts))
+    elif name == "V3":
+        # C3 on the bounded domain: the ring of Omega_I data is drawn like
+        # the interior and then held fixed (volume constraint)
+        nn = n or 128
+        r = 8
+        amp = constant_amp(nn, r, 1.0 + XI_PAPER)
+        m = Model(n=nn, delta=r / nn, kernel=KERNEL_CONSTANT, amp=amp,
+                  sigma=0.0, c_F=1.0, tau=0.02, boundary=1)
+        S = 4096 if n_samples is None else n_samples
+        samples = []
+        for s in range(S):
+            cF = float(rng_for(7 + 1000, s).uniform(0.95, 1.05))
+            samples.append(Sample(0, cF, amp, "iid", 7, s))
+        w = Workload("V3", [m], samples, nsteps or 500, precision or "f32",
+                     "4096 samples of 128x128 on Omega=(0,1)^2 with a volume "
+                     "constraint (ring of 8 fixed rows, 144x144 stored), delta=8h "
+                     "(197-point disc), constant kernel, per-sample c_F~U[0.95,1.05],"
+                     " iid initial data, 500 steps of tau=0.02")
     elif name == "C5":
         nn = n or 2048
         r = 32

@@ -31,7 +31,7 @@ class DeviceBatch:
         self.dtype = getattr(torch, TORCH_DTYPE[self.prec])
         host = np.empty(self.total, dtype=NP_DTYPE[self.prec])
         for i, s in enumerate(w.samples):
-            n = w.models[s.model].n
+            n = synth.state_side(w.models[s.model])
             off = self.samples[i].offset
             host[off:off + n * n] = synth.initial_state(w, s).astype(
                 NP_DTYPE[self.prec]).reshape(-1)
@@ -62,7 +62,8 @@ class DeviceBatch:
         return e.view(k + 1, len(self.w.samples))
 
     def sample_state(self, i):
-        n = self.w.models[self.w.samples[i].model].n
+        """Sample i's stored array (with the ring under a volume constraint)."""
+        n = synth.state_side(self.w.models[self.w.samples[i].model])
         off = self.samples[i].offset
         return self.state[off:off + n * n].double().cpu().numpy().reshape(n, n)
 

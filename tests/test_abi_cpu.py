@@ -33,7 +33,8 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(nlch.nlch_model) == 64
+    assert ctypes.sizeof(nlch.nlch_model) == 72
+    assert nlch.nlch_model.boundary.offset == 64
     assert ctypes.sizeof(nlch.nlch_sample) == 32
     assert ctypes.sizeof(nlch.mfmc_result) == 8 * (2 + 5 * nlch.NLCH_MFMC_MAX_K)
 
@@ -197,3 +198,36 @@ def test_beta2_validation():
     S2 = [nlch.nlch_sample(0, 0, 1.5, amp, 0)]
     assert _err(nlch.nlch_solve_batch, [ok], S2, 5, 1, 0, b, 2 * b,
                 3 * b) == nlch.NLCH_EUNSUPPORTED
+
+
+def test_volume_constraint_validation(orc):
+    """The bounded-domain mode: field checks, the same model constants as the
+    torus (the full disc lies in Omega and Omega_I), state extents of
+    (n + 2m)^2 elements, and the combinations it is not built for, all
+    rejected before any device work."""
+    E, U = nlch.NLCH_EINVAL, nlch.NLCH_EUNSUPPORTED
+    n, delta = 32, 3 / 32
+    per = nlch.make_model(n, delta, 0, 1.0, tau=0.01)
+    vol = nlch.make_model(n, delta, 0, 1.0, tau=0.01, boundary=nlch.NLCH_BOUNDARY_VOLUME)
+    assert nlch.nlch_model_constants(vol) == nlch.nlch_model_constants(per)
+    bad = nlch.make_model(n, delta, 0, 1.0, tau=0.01, boundary=2)
+    assert _err(nlch.nlch_model_constants, bad) == E
+    bad = nlch.make_model(n, delta, 0, 1.0, tau=0.01, boundary=1)
+    bad.reserved = 3
+    assert _err(nlch.nlch_model_constants, bad) == E
+    b2 = nlch.make_model(n, delta, 0, 1.0, beta2=0.05, tau=0.01, boundary=1)
+    assert _err(nlch.nlch_model_constants, b2) == U
+    side = n + 2 * 3
+    big = 1 << 30
+    # n^2 apart: disjoint on the torus, overlapping with the ring
+    S = [nlch.nlch_sample(0, 0, 1.0, 1.0, 0), nlch.nlch_sample(0, 0, 1.0, 1.0, n * n)]
+    f = nlch.nlch_solve_batch
+    assert _err(f, [vol], S, 5, 1, 0, big, big * 2, big * 3) == E
+    S = [nlch.nlch_sample(0, 0, 1.0, 1.0, 0),
+         nlch.nlch_sample(0, 0, 1.0, 1.0, side * side)]
+    assert _err(f, [vol], S, 5, 1, nlch.NLCH_ALGO_RESIDENT, big, big * 2, big * 3) == U
+    assert _err(nlch.nlch_solve_batch_energy, [vol], S, 5, 1, 0, big, big * 2, big * 3,
+                big * 4) == U
+    assert _err(f, [vol], S, 5, 1, 0, big, None, big * 3) == E
+    # nlch_step: buffers n^2 FP32 elements apart overlap with the ring
+    assert _err(nlch.nlch_step, vol, 1, 0, 4096, 4096 + 4 * n * n) == E

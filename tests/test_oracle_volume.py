@@ -180,3 +180,17 @@ def test_solve_projects_and_reduces_over_omega():
     assert np.all(np.abs(U) <= 1.0)
     assert mean == pytest.approx(U[m:m + n, m:m + n].mean(), rel=1e-15)
     assert f1 == pytest.approx(0.5 * (1 + mean), rel=1e-15)
+
+
+def test_site_evaluation_matches_the_full_step():
+    """step_sites reproduces the full step at random nodes, including nodes
+    next to the ring and the corners."""
+    n, R2 = 40, 25
+    md = _model(n, R2, 1, amp=40.0, sigma=0.1)
+    m = 5
+    U = _state(n, m, 21, amp=1.0)
+    full = vol.step(U, c_F=1.0, **md, **TB)[m:m + n, m:m + n].ravel()
+    sites = np.concatenate([[0, n - 1, n * n - 1, n * (n - 1)],
+                            np.random.default_rng(2).choice(n * n, 200, replace=False)])
+    got = vol.step_sites(U, sites, c_F=1.0, **md, **TB)
+    np.testing.assert_allclose(got, full[sites], rtol=0, atol=1e-15)
