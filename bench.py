@@ -35,9 +35,10 @@ if ROOT not in sys.path:
 
 METRIC = ("site-steps/s & HBM/LDS GB/s: batched FP32 vs 1-sample FP64, "
           "OoI err stated")
-# VALU lane-operation issue rate of MI355X without packed FP32 instructions:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP32 add/mul/FMA per lane-op).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector peak of MI355X in lane-operations (one add, multiply or fused
+# multiply-add each): 256 CUs x 128 FP32 lanes per clock x 2.4 GHz = 78.6 T/s,
+# the published 157.3 TFLOP/s with a fused multiply-add counted as one.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 

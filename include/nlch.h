@@ -48,8 +48,8 @@
  * and the update are those of the torus; only Omega's nodes are updated, the
  * ring is copied (after the initial projection onto [-1, 1], which covers
  * every node), and the output of interest is the mean over Omega's n^2
- * nodes.  This mode needs beta2 = 0 and is built for the DIRECT and ROWRUN
- * algorithms without the energy trace.
+ * nodes.  This mode needs beta2 = 0 and runs without the energy trace; every
+ * algorithm applies (RESIDENT for n = 64 and 128).
  *
  * Conventions for every entry point:
  *  - Status: 0 on success, else one of the NLCH_E* codes; the message of the
@@ -198,8 +198,9 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
  * state: device buffer holding every sample's state at its offset
  * (in: u0, out: final state).  scratch: device buffer of the same extent,
  * used as the ping-pong partner (may be NULL when every sample runs
- * RESIDENT; under NLCH_BOUNDARY_VOLUME the projected ring is written to both
- * buffers).  ooi_out: device array of 2*n_samples doubles.
+ * RESIDENT; under NLCH_BOUNDARY_VOLUME the streaming kernels write the
+ * projected ring to both buffers, the resident kernel to state only).
+ * ooi_out: device array of 2*n_samples doubles.
  * Samples of different models (uneven n and horizon) may be mixed; the
  * library never reorders outputs.  Without NLCH_ALGO_NOGRAPH the sequence of
  * launches is captured once into a HIP graph per distinct call signature

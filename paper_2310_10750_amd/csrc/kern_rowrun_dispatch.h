@@ -80,9 +80,11 @@ template <int R2, class TS, class TA, bool GAUSS>
 hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
                            hipStream_t s, double *energy, int64_t estride) {
     constexpr int M = Disc<R2>::M;
-    const int threads = 64 * (g.n / kResB);
-    const size_t lds = resident_lds_bytes(g.n, M, kResB, sizeof(TS), sizeof(TA));
-    if ((g.n != 64 && g.n != 128) || g.lo != 0 || lds > kLdsBytes - 1024)
+    const bool vol = g.lo != 0;  // Omega's g.ni x g.ni lattice inside a ring of m
+    const int threads = 64 * (g.ni / kResB);
+    const size_t lds = resident_lds_bytes(g.ni, M, kResB, sizeof(TS), sizeof(TA), vol);
+    if ((g.ni != 64 && g.ni != 128) || (vol && (g.lo != M || energy)) ||
+        lds > kLdsBytes - 1024)
         return hipErrorInvalidValue;
     auto go = [&](auto f) {
         // per kernel (every instantiation has the same pointer type, so no
@@ -92,16 +94,21 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
         hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(threads), lds, s, g.sd, g.ids,
                            g.geo, (TS *)state, nsteps, ooi, energy, estride);
     };
-    if (energy) {
-        if (g.n == 64)
-            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true>);
+    if (vol) {
+        if (g.ni == 64)
+            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, true>);
         else
-            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true>);
+            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, true>);
+    } else if (energy) {
+        if (g.ni == 64)
+            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>);
+        else
+            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true, false>);
     } else {
-        if (g.n == 64)
-            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false>);
+        if (g.ni == 64)
+            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, false>);
         else
-            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false>);
+            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, false>);
     }
     return hipGetLastError();
 }
@@ -116,7 +123,7 @@ bool rowrun_has_typed(int R2) {
 }
 
 template <class TS, class TA>
-bool resident_has_typed(int R2, int n) {
+bool resident_has_typed(int R2, int n, bool vol) {
     bool in_list = false;
 #define NLCH_X(v) \
     if (R2 == v) in_list = true;
@@ -125,7 +132,8 @@ bool resident_has_typed(int R2, int n) {
     // built for n = 64 and n = 128 (whole bands, one wave per band)
     if (!in_list || (n != 64 && n != 128)) return false;
     const int M = cisqrt(R2);
-    return M <= kResB && resident_lds_bytes(n, M, kResB, sizeof(TS), sizeof(TA)) <= kLdsBytes - 1024;
+    return M <= kResB &&
+           resident_lds_bytes(n, M, kResB, sizeof(TS), sizeof(TA), vol) <= kLdsBytes - 1024;
 }
 
 template <class TS, class TA>
@@ -168,7 +176,9 @@ hipError_t resident_typed(const Group &g, void *state, int nsteps, double *ooi,
         return cnt;                                                                         \
     }                                                                                       \
     bool rowrun_has_##SUFFIX(int R2) { return rowrun_has_typed<TS, TA>(R2); }               \
-    bool resident_has_##SUFFIX(int R2, int n) { return resident_has_typed<TS, TA>(R2, n); } \
+    bool resident_has_##SUFFIX(int R2, int n, bool vol) {                                   \
+        return resident_has_typed<TS, TA>(R2, n, vol);                                      \
+    }                                                                                       \
     hipError_t rowrun_step_##SUFFIX(const Group &g, const void *in, void *out,              \
                                     hipStream_t s, double *epart) {                         \
         return rowrun_step_typed<TS, TA>(g, in, out, s, epart);                             \

@@ -537,6 +537,13 @@ __global__ __launch_bounds__(512) void k_band(
 // input row is read and turned into window sums exactly once per step.
 // The initial projection and the final FP64 output-of-interest reduction
 // are fused in.
+//
+// VOL (volume constraint): the stored array is (n + 2m)^2 with the n x n
+// lattice of Omega inside a ring of m rows and columns of fixed values.  The
+// ring columns of a band's rows sit in the LDS halo for the whole solve, and
+// the ring rows above and below Omega, whose contribution to the first and
+// last m rows never changes, are turned into window sums once, before the
+// first step; bands 0 and n/B - 1 add those instead of a neighbour's sums.
 // ---------------------------------------------------------------------------
 
 // LDS row stride of the resident kernel: n plus the 2m halo, rounded up to
@@ -546,13 +553,15 @@ __host__ __device__ constexpr int resident_row_stride(int n, int M) {
 }
 
 // LDS bytes of the resident kernel: the state rows, then for every band an
-// "up" and a "down" exchange block of m rows of n partial sums.
+// "up" and a "down" exchange block of m rows of n partial sums (and with a
+// volume constraint the fixed sums of the ring rows above and below).
 __host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, size_t ts,
-                                                        size_t ta) {
-    return (size_t)n * resident_row_stride(n, M) * ts + 2 * (size_t)(n / B) * M * n * ta;
+                                                        size_t ta, bool vol = false) {
+    return (size_t)n * resident_row_stride(n, M) * ts +
+           (2 * (size_t)(n / B) + (vol ? 2 : 0)) * M * n * ta;
 }
 
-template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY>
+template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY, bool VOL>
 __global__ __launch_bounds__(512) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
@@ -565,6 +574,9 @@ __global__ __launch_bounds__(512) void k_resident(
     constexpr int Q = B + 2 * M;  // outputs fed by one band: its rows +- m
     static_assert(M <= B, "partial sums must only reach the adjacent bands");
     static_assert(N % B == 0 && N <= 64 * R, "one wave per band");
+    static_assert(!(VOL && ENERGY), "no energy trace under a volume constraint");
+    constexpr int S = VOL ? N + 2 * M : N;  // side of the stored array
+    constexpr int OFF = VOL ? M : 0;        // its row and column of Omega's (0, 0)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
 
@@ -574,6 +586,8 @@ __global__ __launch_bounds__(512) void k_resident(
     TS *lds = reinterpret_cast<TS *>(smem_raw);
     TA *xup = reinterpret_cast<TA *>(smem_raw + (size_t)n * TW * sizeof(TS));
     TA *xdn = xup + (size_t)NB * M * n;
+    TA *rtop = xdn + (size_t)NB * M * n;  // VOL: ring rows above, outputs 0..m-1
+    TA *rbot = rtop + (size_t)M * n;      // VOL: ring rows below, outputs n-m..n-1
     const int sidx = ids[blockIdx.x];
     const SampleDesc d = sd[sidx];
     TS *g_state = state + d.offset;
@@ -598,27 +612,105 @@ __global__ __launch_bounds__(512) void k_resident(
         for (int c = 0; c < R; ++c) {
             const int x = xb + c;
             TA v = TA(0);
-            if (x < n) v = to_acc<TA>(g_state[(int64_t)(y0 + q) * n + x]);
+            if (x < n) v = to_acc<TA>(g_state[(int64_t)(y0 + q + OFF) * S + x + OFF]);
             st[q][c] = clamp1(v);
         }
+
+    if constexpr (VOL) {
+        // The projected ring: columns of this band's rows into the LDS halo
+        // (and back to HBM, projected), for the whole solve.
+        for (int k = threadIdx.x & 63; k < B * 2 * M; k += 64) {
+            const int q = k / (2 * M), j = k - q * 2 * M;
+            const int col = j < M ? j : N + j;  // stored column = LDS column
+            TS *gp = g_state + (int64_t)(y0 + q + M) * S + col;
+            const TS v = to_store<TS>(clamp1(to_acc<TA>(*gp)));
+            lds[(y0 + q) * TW + col] = v;
+            *gp = v;
+        }
+        // Window sums of the ring rows above (band 0) and below (last band),
+        // accumulated into the outputs of Omega's first and last m rows.
+        // r0: Omega row index of the first ring row; qlo: first output row
+        // (both compile-time, so that every register index below is static)
+        auto ring_rows = [&](auto R0, auto QLO, TA *dst) {
+            constexpr int r0 = decltype(R0)::value, qlo = decltype(QLO)::value;
+            TA ac[M][R];
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int c = 0; c < R; ++c) ac[q][c] = TA(-0.0);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                // input row r0 + i (Omega row index; stored row r0 + i + m)
+                TS *gp = g_state + (int64_t)(r0 + i + M) * S + xr;
+                TA win[WIN];
+#pragma unroll
+                for (int k = 0; k < WIN; ++k) win[k] = clamp1(to_acc<TA>(gp[k]));
+                // the projected ring back to HBM (the lanes' windows overlap:
+                // lanes storing the same element store the same value)
+#pragma unroll
+                for (int k = 0; k < WIN; ++k) gp[k] = to_store<TS>(win[k]);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
+                        const int q = r0 + i - dy - qlo;
+                        if (q >= 0 && q < M) ac[q][c] += v;
+                    });
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const int x = xb + c;
+                if (x < n) {
+#pragma unroll
+                    for (int q = 0; q < M; ++q) dst[q * n + x] = ac[q][c];
+                }
+            }
+        };
+        if (band == 0)
+            ring_rows(std::integral_constant<int, -M>{}, std::integral_constant<int, 0>{}, rtop);
+        if (band == NB - 1)
+            ring_rows(std::integral_constant<int, N>{}, std::integral_constant<int, N - M>{},
+                      rbot);
+    }
 
     // With the energy trace, one more pass evaluates E_h(u^nsteps); its
     // update is discarded and the state is written back from the LDS copy.
     const int passes = nsteps + (ENERGY ? 1 : 0);
     for (int step = 0; step < passes; ++step) {
-        // Publish the state (and its periodic column halo) to LDS.  A column
-        // without a halo copy writes its value twice to the same place.
+        // Publish the state to LDS.  The lanes next to the lattice edge then
+        // write the periodic column halo in a store of their own (a volume
+        // constraint keeps the fixed ring columns there instead): folded into
+        // every lane's store, the halo copies hit LDS banks that other lanes
+        // of the same store use at other addresses.
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const int x = xb + c;
-            if (x < n) {
-                const int xh = x < M ? x + n : (x >= n - M ? x - n : x);
+            if (N == 64 * R || x < n) {
 #pragma unroll
-                for (int q = 0; q < B; ++q) {
-                    TS *row = lds + (y0 + q) * TW + M;
-                    const TS v = to_store<TS>(st[q][c]);
-                    row[x] = v;
-                    row[xh] = v;
+                for (int q = 0; q < B; ++q)
+                    lds[(y0 + q) * TW + M + x] = to_store<TS>(st[q][c]);
+            }
+        }
+        if constexpr (!VOL && M % R == 0 && N == 64 * R) {
+            // a lane's R columns are all halo columns or none: one store of
+            // R adjacent values per row
+            if (xb < M || xb >= n - M) {
+                const int xh = xb < M ? xb + n : xb - n;
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+#pragma unroll
+                    for (int c = 0; c < R; ++c)
+                        lds[(y0 + q) * TW + M + xh + c] = to_store<TS>(st[q][c]);
+            }
+        } else if constexpr (!VOL) {
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const int x = xb + c;
+                if (x < M || (x >= n - M && x < n)) {
+                    const int xh = x < M ? x + n : x - n;
+#pragma unroll
+                    for (int q = 0; q < B; ++q)
+                        lds[(y0 + q) * TW + M + xh] = to_store<TS>(st[q][c]);
                 }
             }
         }
@@ -631,17 +723,19 @@ __global__ __launch_bounds__(512) void k_resident(
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[q][c] = TA(-0.0);
         const TS *rp0 = lds + y0 * TW + xr;
+        // The window of row i + 1 is loaded while row i is summed (two
+        // window buffers); the empty asm keeps the compiler from hoisting
+        // every row's loads, and their registers, to the top of the walk.
+        TA win[2][WIN];
+        load_window<WIN, (R % 2 == 0)>(rp0, win[0]);
 #pragma unroll
         for (int i = 0; i < B; ++i) {
-            // rows are independent: keep the compiler from hoisting every
-            // row's loads (and their registers) to the top of the walk
             asm volatile("" ::: "memory");
-            TA win[WIN];
-            load_window<WIN, (R % 2 == 0)>(rp0 + i * TW, win);
+            if (i + 1 < B) load_window<WIN, (R % 2 == 0)>(rp0 + (i + 1) * TW, win[(i + 1) & 1]);
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 // input row i feeds output q = i - dy
-                row_windows<R2, GAUSS>(win + c, g, [&](int dy, TA v) {
+                row_windows<R2, GAUSS>(win[i & 1] + c, g, [&](int dy, TA v) {
                     acc[M + i - dy][c] += v;
                 });
             }
@@ -659,13 +753,19 @@ __global__ __launch_bounds__(512) void k_resident(
             }
         }
         __syncthreads();
+        const TA *above = xdn + (size_t)bdn * M * n;
+        const TA *below = xup + (size_t)bup * M * n;
+        if constexpr (VOL) {
+            if (band == 0) above = rtop;
+            if (band == NB - 1) below = rbot;
+        }
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const int x = xr + c;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                acc[M + j][c] += xdn[((size_t)bdn * M + j) * n + x];
-                acc[B + j][c] += xup[((size_t)bup * M + j) * n + x];
+                acc[M + j][c] += above[(size_t)j * n + x];
+                acc[B + j][c] += below[(size_t)j * n + x];
             }
         }
         // (energy trace) E_h of the state this pass started from, from the
@@ -703,7 +803,7 @@ __global__ __launch_bounds__(512) void k_resident(
             const int x = xb + c;
             if (x < n) {
                 const TA v = ENERGY ? to_acc<TA>(lds[(y0 + q) * TW + M + x]) : st[q][c];
-                g_state[(int64_t)(y0 + q) * n + x] = to_store<TS>(v);
+                g_state[(int64_t)(y0 + q + OFF) * S + x + OFF] = to_store<TS>(v);
                 part += (double)v;
             }
         }

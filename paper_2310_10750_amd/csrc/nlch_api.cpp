@@ -24,7 +24,7 @@ namespace nlch {
 #define NLCH_DECL(SUF)                                                                   \
     int rowrun_r2_##SUF(int64_t *out, int cap);                                          \
     bool rowrun_has_##SUF(int R2);                                                       \
-    bool resident_has_##SUF(int R2, int n);                                              \
+    bool resident_has_##SUF(int R2, int n, bool vol);                                    \
     hipError_t rowrun_step_##SUF(const Group &g, const void *in, void *out, hipStream_t s, \
                                  double *epart);                                         \
     hipError_t resident_##SUF(const Group &g, void *state, int nsteps, double *ooi,      \
@@ -45,11 +45,11 @@ bool rowrun_supported(int prec, bool acc64, int R2, int) {
     }
 }
 
-bool resident_supported(int prec, bool acc64, int R2, int, int n) {
+bool resident_supported(int prec, bool acc64, int R2, int, int n, bool vol) {
     switch (prec) {
-        case kF64: return resident_has_f64(R2, n);
-        case kF32: return !acc64 && resident_has_f32(R2, n);
-        default: return !acc64 && resident_has_f16(R2, n);
+        case kF64: return resident_has_f64(R2, n, vol);
+        case kF32: return !acc64 && resident_has_f32(R2, n, vol);
+        default: return !acc64 && resident_has_f16(R2, n, vol);
     }
 }
 
@@ -310,8 +310,8 @@ int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nl
         *variant = kB2;
         return NLCH_OK;
     }
-    const bool res = batch && mi.lo == 0 &&
-                     resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n);
+    const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n,
+                                                 mi.lo != 0);
     const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
     switch (base) {
         case NLCH_ALGO_AUTO:
@@ -330,9 +330,8 @@ int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nl
             if (!batch) return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
             if (!res)
                 return fail(NLCH_EUNSUPPORTED,
-                            "RESIDENT needs the periodic domain, n <= 128, a sample that fits "
-                            "in LDS and a built R2 (n = %d, R2 = %lld)", md.n,
-                            (long long)mi.R2);
+                            "RESIDENT needs n = 64 or 128, a sample that fits in LDS and a "
+                            "built R2 (n = %d, R2 = %lld)", md.n, (long long)mi.R2);
             *variant = kResident;
             return NLCH_OK;
         default:

@@ -163,7 +163,7 @@ bool rowrun_supported(int prec, bool acc64, int R2, int kernel);
 hipError_t launch_rowrun_step(int prec, bool acc64, const Group &g,
                               const void *in, void *out, hipStream_t s,
                               double *epart = nullptr);
-bool resident_supported(int prec, bool acc64, int R2, int kernel, int n);
+bool resident_supported(int prec, bool acc64, int R2, int kernel, int n, bool vol);
 // `energy` (nullable): E_h(u^k) of sample s at energy[k * estride + s].
 hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
                            int nsteps, double *ooi, hipStream_t s,
