@@ -75,9 +75,9 @@ def algorithmic_ops(m: int, kernel: int) -> int:
     return 2 * m + (2 * m + 1) + 6
 
 
-def stored_traffic(kernel_name: str):
+def stored_traffic(kernel_name: str, workload: str):
     """HBM bytes per launch of the kernel from the committed counter summary,
-    if it was measured on the current kernel sources."""
+    if it was measured on this workload and on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -87,6 +87,8 @@ def stored_traffic(kernel_name: str):
         return None
     e = d.get(kernel_name)
     if not e or e.get("source_hash") != kernel_source_hash(kernel_name):
+        return None
+    if not e.get("workload", "").startswith(workload + ":"):
         return None
     return e.get("bytes_per_launch")
 
@@ -193,18 +195,22 @@ def main():
     # Dominant kernel: with every sample LDS-resident the solve is one launch.
     m0 = w.models[0]
     R2, mdisc, N, _ = nlch.nlch_disc(m0.n, m0.delta)
-    resident = all(mm.n in (64, 128) and not mm.boundary for mm in w.models) and \
+    resident = all(mm.n in (64, 128) and mm.beta2 == 0 for mm in w.models) and \
         (args.algo & 0xff) in (0, 3)
     kname = "k_resident" if resident else "k_rowrun"
     ops = sum(algorithmic_ops(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
                               w.models[s.model].kernel) * w.models[s.model].n ** 2
               for s in w.samples) * w.nsteps
     achieved = ops / (solve_ms * 1e-3) / 1e12
-    traffic = stored_traffic(kname)
+    traffic = stored_traffic(kname, w.name)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic, "kernel": kname,
                 "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel)}
+    if any(mm.beta2 > 0 for mm in w.models):
+        # an iterative solve per step (Newton with conjugate-gradient inner
+        # solves): no fixed algorithmic count per site-step to price
+        roofline = None
     state_bytes = total * np.dtype(ndt).itemsize
     hbm_gbs = 2 * state_bytes / (solve_ms * 1e-3) / 1e9
 
@@ -257,7 +263,11 @@ def main():
         rel, tcpu, sscpu, k = [], 0.0, 0, 0
         cores = oracle.threads()
         cap = min(args.cpu_samples, S)
-        chunk = 4 if any(mm.boundary for mm in w.models) else 16
+        chunk = 16
+        if any(mm.boundary for mm in w.models):
+            chunk = 4
+        if any(mm.beta2 > 0 for mm in w.models):
+            chunk = 1
         # chunks of consecutive samples (all steps each) until the time
         # budget is spent; the sample count is reported
         while k < cap and tcpu < args.cpu_seconds:
@@ -270,7 +280,15 @@ def main():
                 u0 = np.stack([synth.initial_state(w, w.samples[i]).astype(ndt)
                                .astype(np.float64) for i in ids])
                 t = time.perf_counter()
-                if mm.boundary:
+                if mm.beta2 > 0:
+                    # the beta2 > 0 oracle (sparse direct Newton solves, one thread)
+                    from oracle import b2
+                    f1 = [b2.solve_b2(u0[j], w.nsteps, mm.n, mm.delta, mm.kernel,
+                                      w.samples[i].amp, mm.sigma, w.samples[i].c_F,
+                                      mm.beta1, mm.beta2, mm.tau)[2]
+                          for j, i in enumerate(ids)]
+                    cores = 1
+                elif mm.boundary:
                     # the bounded-domain oracle (numpy, one thread)
                     from oracle import volume
                     f1 = [volume.solve(u0[j], w.nsteps, mm.n, mm.delta, mm.kernel,

@@ -278,6 +278,21 @@ def workload(name: str, n_samples: int = None, nsteps: int = None,
                      "constraint (ring of 8 fixed rows, 144x144 stored), delta=8h "
                      "(197-point disc), constant kernel, per-sample c_F~U[0.95,1.05],"
                      " iid initial data, 500 steps of tau=0.02")
+    elif name == "B2":
+        # the paper's experimental model: beta1 = 1, beta2 = 0.05, Gaussian
+        # kernel of delta = delta_hf = 0.25 (eps^2 = 0.00178), tau = 0.01,
+        # four-nuclei data, on the high-fidelity 128^2 lattice
+        nn = n or 128
+        amp, sigma, _ = gaussian_params(0.25)
+        m = Model(n=nn, delta=0.25, kernel=KERNEL_GAUSSIAN, amp=amp, sigma=sigma,
+                  c_F=1.0, beta2=0.05, tau=0.01)
+        S = 2048 if n_samples is None else n_samples
+        samples = [Sample(0, 1.0, amp, "nuclei", 6, s, draw_theta(rng_for(6, s)))
+                   for s in range(S)]
+        w = Workload("B2", [m], samples, nsteps or 10, precision or "f32",
+                     "2048 samples of 128x128, beta1=1, beta2=0.05, delta=0.25 (32h, "
+                     "3209-point disc), Gaussian kernel, four-nuclei initial data, "
+                     "10 steps of tau=0.01")
     elif name == "C5":
         nn = n or 2048
         r = 32
