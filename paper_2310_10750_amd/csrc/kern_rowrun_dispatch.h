@@ -82,7 +82,8 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
     constexpr int M = Disc<R2>::M;
     const bool vol = g.lo != 0;  // Omega's g.ni x g.ni lattice inside a ring of m
     const int threads = 64 * (g.ni / kResB);
-    const size_t lds = resident_lds_bytes(g.ni, M, kResB, sizeof(TS), sizeof(TA), vol);
+    const size_t lds =
+        resident_lds_bytes(g.ni, M, kResB, sizeof(TS), sizeof(TA), energy != nullptr, vol);
     if ((g.ni != 64 && g.ni != 128) || (vol && (g.lo != M || energy)) ||
         lds > kLdsBytes - 1024)
         return hipErrorInvalidValue;
@@ -133,7 +134,10 @@ bool resident_has_typed(int R2, int n, bool vol) {
     if (!in_list || (n != 64 && n != 128)) return false;
     const int M = cisqrt(R2);
     return M <= kResB &&
-           resident_lds_bytes(n, M, kResB, sizeof(TS), sizeof(TA), vol) <= kLdsBytes - 1024;
+           // the largest layout of the variants (the energy trace keeps a
+           // separate exchange area)
+           resident_lds_bytes(n, M, kResB, sizeof(TS), sizeof(TA), !vol, vol) <=
+               kLdsBytes - 1024;
 }
 
 template <class TS, class TA>

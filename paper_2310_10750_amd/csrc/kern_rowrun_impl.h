@@ -552,17 +552,35 @@ __host__ __device__ constexpr int resident_row_stride(int n, int M) {
     return (n + 2 * M + 1) & ~1;
 }
 
-// LDS bytes of the resident kernel: the state rows, then for every band an
-// "up" and a "down" exchange block of m rows of n partial sums (and with a
-// volume constraint the fixed sums of the ring rows above and below).
-__host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, size_t ts,
-                                                        size_t ta, bool vol = false) {
-    return (size_t)n * resident_row_stride(n, M) * ts +
-           (2 * (size_t)(n / B) + (vol ? 2 : 0)) * M * n * ta;
+// In-place exchange: a band reads only its own rows of the LDS state while
+// it walks them, so once its walk is done it can hand its partial sums over
+// in those rows (2m x n values in B rows of the state's type) instead of in
+// an area of their own.  That halves the LDS of the kernel, so that two
+// workgroups share a CU (four waves per SIMD).  Used where the partial sums
+// fit and have the state's type, without the energy trace or a volume
+// constraint (whose variants keep more values in registers).
+__host__ __device__ constexpr bool resident_inplace(int n, int M, int B, size_t ts, size_t ta,
+                                                    bool energy, bool vol) {
+    return !energy && !vol && ts == ta && 2 * M * n <= B * resident_row_stride(n, M);
 }
 
-template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY, bool VOL>
-__global__ __launch_bounds__(512) void k_resident(
+// LDS bytes of the resident kernel: the state rows, then (unless the
+// exchange is in place) for every band an "up" and a "down" exchange block of
+// m rows of n partial sums, and with a volume constraint the fixed sums of the
+// ring rows above and below.
+__host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, size_t ts,
+                                                        size_t ta, bool energy = false,
+                                                        bool vol = false) {
+    return (size_t)n * resident_row_stride(n, M) * ts +
+           (resident_inplace(n, M, B, ts, ta, energy, vol)
+                ? 0
+                : (2 * (size_t)(n / B) + (vol ? 2 : 0)) * M * n * ta);
+}
+
+template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY, bool VOL,
+          bool INPLACE = resident_inplace(N, Disc<R2>::M, B, sizeof(TS), sizeof(TA), ENERGY,
+                                          VOL)>
+__global__ __launch_bounds__(512, INPLACE ? 4 : 1) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
     double *__restrict__ ooi, double *__restrict__ energy, int64_t estride) {
@@ -740,21 +758,37 @@ __global__ __launch_bounds__(512) void k_resident(
                 });
             }
         }
-        // Hand the overhanging partial sums to the adjacent bands.
+        // Hand the overhanging partial sums to the adjacent bands (in place:
+        // in this band's own rows, after taking back its sites' values).
+        TA *myup = xup + (size_t)band * M * n, *mydn = xdn + (size_t)band * M * n;
+        const TA *above = xdn + (size_t)bdn * M * n;
+        const TA *below = xup + (size_t)bup * M * n;
+        if constexpr (INPLACE) {
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+#pragma unroll
+                for (int c = 0; c < R; ++c) st[q][c] = to_acc<TA>(lds[(y0 + q) * TW + M + xr + c]);
+            // the wave's own reads of its rows come before its writes there
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            myup = reinterpret_cast<TA *>(lds + y0 * TW);
+            mydn = myup + (size_t)M * n;
+            above = reinterpret_cast<const TA *>(lds + bdn * B * TW) + (size_t)M * n;
+            below = reinterpret_cast<const TA *>(lds + bup * B * TW);
+        }
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const int x = xb + c;
             if (x < n) {
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
-                    xup[((size_t)band * M + j) * n + x] = acc[j][c];
-                    xdn[((size_t)band * M + j) * n + x] = acc[B + M + j][c];
+                    myup[(size_t)j * n + x] = acc[j][c];
+                    mydn[(size_t)j * n + x] = acc[B + M + j][c];
                 }
             }
         }
         __syncthreads();
-        const TA *above = xdn + (size_t)bdn * M * n;
-        const TA *below = xup + (size_t)bup * M * n;
         if constexpr (VOL) {
             if (band == 0) above = rtop;
             if (band == NB - 1) below = rbot;
@@ -768,6 +802,9 @@ __global__ __launch_bounds__(512) void k_resident(
                 acc[B + j][c] += below[(size_t)j * n + x];
             }
         }
+        // (in place) the neighbours have read this band's rows before it
+        // publishes the next state there
+        if constexpr (INPLACE) __syncthreads();
         // (energy trace) E_h of the state this pass started from, from the
         // per-site terms u Lsum and 1 - u^2 accumulated in FP64
         double e_ul = 0.0, e_pot = 0.0;
