@@ -32,7 +32,11 @@
  * xi_h <= 0 (a non-convex step with possibly several solutions) are
  * NLCH_EUNSUPPORTED.  A sample whose Newton iteration does not converge
  * within its iteration cap gets a NaN state and output of interest.
- * Per sample the library keeps 7 n^2 doubles of workspace with the batch.
+ * Per sample the library keeps 7 n^2 doubles of workspace with the batch;
+ * within one nlch_solve_batch call Newton starts each step from the previous
+ * step's z held there (from xi_h u at the call's first step), so a solve split
+ * over several calls agrees with one call to the Newton tolerance (~1e-13
+ * relative), not bit for bit.
  *
  * Bounded domain (NLCH_BOUNDARY_VOLUME; Sec. 2.1: the operator integrates
  * over Omega = (0,1)^2 together with the interaction region Omega_I of points

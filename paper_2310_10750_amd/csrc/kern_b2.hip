@@ -22,6 +22,9 @@
 // flow is uniform across the workgroup; every loop has a fixed cap, and a
 // sample whose Newton iteration has not converged at the cap gets a NaN
 // state (hence a NaN output of interest).
+#include <algorithm>
+#include <type_traits>
+
 #include "nlch_device.h"
 
 namespace nlch {
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
     const TS *__restrict__ in, TS *__restrict__ out, double *__restrict__ ws,
-    double *__restrict__ epart) {
+    double *__restrict__ epart, int warm) {
     __shared__ double red[kB2Waves * 4];
     const int j = blockIdx.x;
     const SampleDesc d = sd[ids[j]];
@@ -138,14 +141,15 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
         }
     }
     __syncthreads();
-    // r = u_old + tau A g, z = xi u_old
+    // r = u_old + tau A g; Newton starts from z = xi u_old, or (warm) from
+    // the previous step's z, which the workspace still holds
     double rr = 0.0;
     for (int i = tid; i < nn; i += kB2Threads) {
         const int y = i / n, x = i - y * n;
         const double ui = (double)u[i];
         const double r = ui + tau_a(Q, i, y, x, n, nn, tb1, tb2n2);
         R[i] = r;
-        Z[i] = xi * ui;
+        if (!warm) Z[i] = xi * ui;  // else z of the previous step, in place
         rr += r * r;
     }
     const double scale = fmax(1.0, sqrt(block_sum1(rr, red)));
@@ -231,24 +235,27 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
 
 // On-chip variant for n = 64, 88, 128: the same iteration, with the conjugate-
 // gradient loop -- all but a few passes of a step -- kept on the compute
-// unit.  512 threads own up to 32 sites each (site t + 512 k); the CG
-// residual (FP64) and solution (FP32) live in registers, the CG direction
-// (FP64; the only vector read at neighbouring sites) in LDS, and the
-// inactive-set mask in a register bitmask.  z, r, F and the Newton direction stay in the
+// unit.  512 threads (1024 at n = 128) own up to 16 sites each (site
+// t + THREADS k); the CG residual (FP64) lives in registers, the CG
+// solution (FP32) and direction (FP32; the only vector read at neighbouring
+// sites) in LDS, and the inactive-set mask in a register bitmask.  z, r, F and the Newton direction stay in the
 // global workspace, touched a few times per Newton step.  The Newton level
 // (F, convergence test, line search, z) is the same FP64 arithmetic as in
 // k_b2_step; only the inner directions differ by rounding.
-constexpr int kB2LdsThreads = 512;
-constexpr int kB2LdsWaves = kB2LdsThreads / 64;
-constexpr int kB2Spt = 32;  // sites per thread: n^2 <= 32 * 512
+// Workgroup size: 1024 threads (16 sites each) from n = 128 on, else 512.
+constexpr int b2_lds_threads(int nn) { return nn >= 128 * 128 ? 1024 : 512; }
+constexpr int kB2LdsMaxWaves = 16;
+constexpr int kB2Spt = 16;  // sites per thread
 
-template <int K>
+// Workgroup sums with one barrier: successive calls must alternate between
+// two `red` areas (a thread writes area A for sum k + 2 only after the
+// barrier of sum k + 1, which every thread passes after reading sum k).
+template <int K, int WAVES>
 __device__ __forceinline__ void block_sums_lds(double (&v)[K], double *red) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
         for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
@@ -256,26 +263,31 @@ __device__ __forceinline__ void block_sums_lds(double (&v)[K], double *red) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int i = 0; i < kB2LdsWaves; ++i) s += red[i * K + k];
+        for (int i = 0; i < WAVES; ++i) s += red[i * K + k];
         v[k] = s;
     }
 }
 
+template <int WAVES>
 __device__ __forceinline__ double sum1_lds(double v, double *red) {
     double a[1] = {v};
-    block_sums_lds<1>(a, red);
+    block_sums_lds<1, WAVES>(a, red);
     return a[0];
 }
 
-template <class TS, bool GAUSS, int NN>
-__global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
+template <class TS, bool GAUSS, int NN, int THREADS = b2_lds_threads(NN * NN)>
+__global__ __launch_bounds__(THREADS) void k_b2_step_lds(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
     const TS *__restrict__ in, TS *__restrict__ out, double *__restrict__ ws,
-    double *__restrict__ epart) {
+    double *__restrict__ epart, int warm) {
+    constexpr int kB2LdsThreads = THREADS, kB2LdsWaves = THREADS / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *Pl = reinterpret_cast<double *>(smem_raw);  // CG direction, (n+2)^2
-    __shared__ double red[kB2LdsWaves * 4];
+    float *Pl = reinterpret_cast<float *>(smem_raw);  // CG direction, (n+2)^2
+    float *Xl = Pl + (NN + 2) * (NN + 2);             // CG solution, n^2 (own sites)
+    __shared__ double red2[2][kB2LdsMaxWaves * 4];
+    int rsel = 0;  // the two areas of the workgroup sums, used in turn
+    auto red = [&]() { rsel ^= 1; return red2[rsel]; };
     const int j = blockIdx.x;
     const SampleDesc d = sd[ids[j]];
     // the lattice size is a compile-time constant, so that the stencil's
@@ -296,30 +308,49 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
     const double *e = ewd + geo->e_off;
     const int tid = threadIdx.x;
 
-    // g and the energy partials of u_old
+    // g and the energy partials of u_old, from copies of u_old (exact: FP64
+    // for FP64 storage, else FP32) and of the weight table in LDS, which the
+    // CG direction reuses afterwards
+    using TU = typename std::conditional<std::is_same<TS, double>::value, double, float>::type;
+    TU *Ul = reinterpret_cast<TU *>(smem_raw);
+    double *El = reinterpret_cast<double *>(smem_raw + sizeof(TU) * nn);
+    for (int i = tid; i < nn; i += kB2LdsThreads) Ul[i] = (TU)(double)u[i];
+    if (GAUSS)
+        for (int i = tid; i < (m + 1) * (m + 1); i += kB2LdsThreads) El[i] = e[i];
+    __syncthreads();
     double e_ul = 0.0, e_pot = 0.0;
-    for (int i = tid; i < nn; i += kB2LdsThreads) {
-        const int y = i / n, x = i - y * n;
-        const double ui = (double)u[i];
-        double acc = 0.0, lsum = 0.0;
-        for (int dy = -m; dy <= m; ++dy) {
-            const int ady = dy < 0 ? -dy : dy;
-            const int w = geo->halfw[ady];
-            const TS *row = u + (int64_t)wrap_once(y + dy, n) * n;
-            for (int dx = -w; dx <= w; ++dx) {
-                const double v = (double)row[wrap_once(x + dx, n)];
-                const double wt = GAUSS ? e[ady * (m + 1) + (dx < 0 ? -dx : dx)] : 1.0;
-                acc += wt * v;
-                lsum += wt * (ui - v);
+    auto gpass = [&](auto EN) {
+        constexpr bool EN_ = decltype(EN)::value;  // with the energy partials
+        for (int i = tid; i < nn; i += kB2LdsThreads) {
+            const int y = i / n, x = i - y * n;
+            const double ui = (double)Ul[i];
+            double acc = 0.0, lsum = 0.0;
+            for (int dy = -m; dy <= m; ++dy) {
+                const int ady = dy < 0 ? -dy : dy;
+                const int w = geo->halfw[ady];
+                const TU *row = Ul + wrap_once(y + dy, n) * n;
+                const double *er = El + ady * (m + 1);
+                for (int dx = -w; dx <= w; ++dx) {
+                    const double v = (double)row[wrap_once(x + dx, n)];
+                    const double wt = GAUSS ? er[dx < 0 ? -dx : dx] : 1.0;
+                    acc += wt * v;
+                    if (EN_) lsum += wt * (ui - v);
+                }
+            }
+            G[i] = gs * acc;
+            if (EN_) {
+                e_ul += ui * lsum;
+                e_pot += 1.0 - ui * ui;
             }
         }
-        G[i] = gs * acc;
-        e_ul += ui * lsum;
-        e_pot += 1.0 - ui * ui;
-    }
+    };
+    if (epart)
+        gpass(std::true_type{});
+    else
+        gpass(std::false_type{});
     if (epart) {
         double v[2] = {e_ul, e_pot};
-        block_sums_lds<2>(v, red);
+        block_sums_lds<2, kB2LdsWaves>(v, red());
         if (tid == 0) {
             epart[2 * (int64_t)j] = v[0];
             epart[2 * (int64_t)j + 1] = v[1];
@@ -332,22 +363,33 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
         const double ui = (double)u[i];
         const double r = ui + tau_a(G, i, y, x, n, nn, tb1, tb2n2);
         R[i] = r;
-        Z[i] = xi * ui;
+        if (!warm) Z[i] = xi * ui;  // else z of the previous step, in place
         rr += r * r;
     }
-    const double scale = fmax(1.0, sqrt(sum1_lds(rr, red)));
+    const double scale = fmax(1.0, sqrt(sum1_lds<kB2LdsWaves>(rr, red())));
 
-    // Sites of this thread (t + 512 k, k < SPT) and their places in the LDS
-    // copy of the CG direction, which carries a one-cell periodic halo
+    // Sites of this thread (t + THREADS k, k < SPT) and their places in the
+    // LDS copy of the CG direction, which carries a one-cell periodic halo
     // ((n+2)^2, row W): the 5-point stencil then needs no wrap-around, and a
     // boundary site writes its value to the halo cell opposite as well.
+    // Where THREADS is a multiple of n and divides n^2 (n = 64, 128), a
+    // thread's sites share one column and step THREADS/n rows, so their LDS
+    // places are one base plus compile-time offsets (no address registers).
     constexpr int W = n + 2;
     constexpr int SPT = (nn + kB2LdsThreads - 1) / kB2LdsThreads;
     static_assert(SPT <= kB2Spt, "sites per thread");
+    constexpr bool EXACT = nn % kB2LdsThreads == 0 && kB2LdsThreads % n == 0;
+    constexpr int RSTEP = kB2LdsThreads / n;  // rows between a thread's sites (EXACT)
     auto pad = [](int i) { return i + 2 * (i / n) + n + 3; };  // (y+1) W + x + 1
-    auto put = [&](int i, double v) {
-        const int q = pad(i);
-        const int y = i / n, x = i - y * n;
+    const int q0 = pad(tid), y0 = tid / n, x0 = tid - (tid / n) * n;
+    auto site = [&](int k) { return tid + kB2LdsThreads * k; };
+    auto valid = [&](int k) { return EXACT || site(k) < nn; };
+    auto qk = [&](int k) { return EXACT ? q0 + k * RSTEP * W : pad(site(k)); };
+    auto put = [&](int k, double vd) {
+        const int q = qk(k);
+        const int y = EXACT ? y0 + k * RSTEP : site(k) / n;
+        const int x = EXACT ? x0 : site(k) - (site(k) / n) * n;
+        const float v = (float)vd;
         Pl[q] = v;
         if (x == 0) Pl[q + n] = v;
         if (x == n - 1) Pl[q - n] = v;
@@ -359,46 +401,49 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
     for (int it = 0;; ++it) {
         // F(z), the CG start (direction -F, to LDS) and the inactive-set mask
         double f2 = 0.0;
-        unsigned mask = 0;  // bit k: site t + 512 k inactive (|z| < xi)
+        unsigned mask = 0;  // bit k: site t + THREADS k inactive (|z| < xi)
 #pragma unroll 1
         for (int k = 0; k < SPT; ++k) {
-            const int i = tid + kB2LdsThreads * k;
-            if (i < nn) {
+            const int i = site(k);
+            if (valid(k)) {
                 const int y = i / n, x = i - y * n;
                 const double zi = Z[i];
                 const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(zi / xi) - R[i];
                 F[i] = f;
-                put(i, -f);
+                put(k, -f);
                 if (fabs(zi) < xi) mask |= 1u << k;
                 f2 += f * f;
             }
         }
-        f2 = sum1_lds(f2, red);  // also makes Pl visible
+        f2 = sum1_lds<kB2LdsWaves>(f2, red());  // also makes Pl visible
         if (sqrt(f2) <= 1e-13 * scale) {
             ok = true;
             break;
         }
         if (it == kMaxNewton) break;
-        // the CG residual in FP64, the direction's running sum in FP32 (a
+        // the CG residual in FP64 (registers), the solution in FP32 (LDS; a
         // Newton direction needs ~1e-7 relative accuracy at most: inexact
-        // Newton then still gains 7 digits a step)
+        // Newton then still gains 7 digits a step).  The CG direction is kept
+        // in FP32: the solution and the residual are updated with the same
+        // rounded direction and its FP64 operator product, so they stay
+        // consistent and the residual reaches FP64 tolerances; the rounding
+        // only perturbs the conjugacy of the directions.
         const double inv_xi = 1.0 / xi;
         double Sr[SPT];
-        float Xr[SPT];
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
-            const int i = tid + kB2LdsThreads * k;
-            Sr[k] = i < nn ? Pl[pad(i)] : 0.0;
-            Xr[k] = 0.0f;
+            Sr[k] = valid(k) ? -F[site(k)] : 0.0;
+            if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
         }
-        // J p at site i from the LDS direction (evaluated twice per
+        // J p at site k from the LDS direction (evaluated twice per
         // iteration, for p.Jp and for the residual update, instead of being
         // kept in registers)
-        auto jp = [&](int i, int k) {
-            const int q = pad(i);
+        auto jp = [&](int k) {
+            const int q = qk(k);
             const double pi = Pl[q];
-            const double ap =
-                tb1 * pi - tb2n2 * (Pl[q + 1] + Pl[q - 1] + Pl[q + W] + Pl[q - W] - 4.0 * pi);
+            const double ap = tb1 * pi - tb2n2 * ((double)Pl[q + 1] + (double)Pl[q - 1] +
+                                                  (double)Pl[q + W] + (double)Pl[q - W] -
+                                                  4.0 * pi);
             return ap + ((mask >> k) & 1u ? pi * inv_xi : 0.0);
         };
         const double eta = fmin(1e-2, sqrt(f2) / scale);
@@ -407,38 +452,31 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
         for (int kk = 0; kk < kMaxCg && rs > stop; ++kk) {
             double pq = 0.0;
 #pragma unroll
-            for (int k = 0; k < SPT; ++k) {
-                const int i = tid + kB2LdsThreads * k;
-                if (i < nn) pq += Pl[pad(i)] * jp(i, k);
-            }
-            pq = sum1_lds(pq, red);
+            for (int k = 0; k < SPT; ++k)
+                if (valid(k)) pq += (double)Pl[qk(k)] * jp(k);
+            pq = sum1_lds<kB2LdsWaves>(pq, red());
             if (!(pq > 0.0)) break;
             const double alpha = rs / pq;
             double rn = 0.0;
 #pragma unroll
             for (int k = 0; k < SPT; ++k) {
-                const int i = tid + kB2LdsThreads * k;
-                if (i < nn) {
-                    Xr[k] = (float)((double)Xr[k] + alpha * Pl[pad(i)]);
-                    Sr[k] -= alpha * jp(i, k);
+                if (valid(k)) {
+                    Xl[site(k)] = (float)((double)Xl[site(k)] + alpha * (double)Pl[qk(k)]);
+                    Sr[k] -= alpha * jp(k);
                     rn += Sr[k] * Sr[k];
                 }
             }
-            rn = sum1_lds(rn, red);  // every thread has read Pl before it changes
+            rn = sum1_lds<kB2LdsWaves>(rn, red());  // every thread has read Pl before it changes
             const double beta = rn / rs;
             rs = rn;
 #pragma unroll
-            for (int k = 0; k < SPT; ++k) {
-                const int i = tid + kB2LdsThreads * k;
-                if (i < nn) put(i, Sr[k] + beta * Pl[pad(i)]);
-            }
+            for (int k = 0; k < SPT; ++k)
+                if (valid(k)) put(k, Sr[k] + beta * (double)Pl[qk(k)]);
             __syncthreads();
         }
 #pragma unroll
-        for (int k = 0; k < SPT; ++k) {
-            const int i = tid + kB2LdsThreads * k;
-            if (i < nn) X[i] = (double)Xr[k];
-        }
+        for (int k = 0; k < SPT; ++k)
+            if (valid(k)) X[site(k)] = (double)Xl[site(k)];
         __syncthreads();
         double sm[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i = tid; i < nn; i += kB2LdsThreads) {
@@ -450,13 +488,13 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
             sm[2] += R[i] * X[i];
             sm[3] += F[i] * X[i];
         }
-        block_sums_lds<4>(sm, red);
+        block_sums_lds<4, kB2LdsWaves>(sm, red());
         double a = 1.0;
         for (int h = 0; h < kMaxHalvings; ++h) {
             double dp = 0.0;
             for (int i = tid; i < nn; i += kB2LdsThreads)
                 dp += phi(Z[i] + a * X[i], xi) - phi(Z[i], xi);
-            dp = sum1_lds(dp, red);
+            dp = sum1_lds<kB2LdsWaves>(dp, red());
             if (a * sm[0] + 0.5 * a * a * sm[1] + dp - a * sm[2] <= 1e-4 * a * sm[3]) break;
             a *= 0.5;
         }
@@ -469,16 +507,24 @@ __global__ __launch_bounds__(kB2LdsThreads) void k_b2_step_lds(
 }
 
 template <class TS>
-hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, double *epart) {
+hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, double *epart,
+                    bool warm) {
     // on-chip variant for the lattices of the multifidelity study
     auto lds_launch = [&](auto f, int n) {
-        const size_t lds = sizeof(double) * (size_t)(n + 2) * (n + 2);
+        // the CG direction and solution (FP32), or, before them, u_old and
+        // the weight table
+        const size_t lds = std::max(
+            sizeof(float) * ((size_t)(n + 2) * (n + 2) + (size_t)n * n),
+            (std::is_same<TS, double>::value ? 8 : 4) * (size_t)n * n +
+                sizeof(double) * (size_t)(g.m + 1) * (g.m + 1));
+        if (lds > 159 * 1024) return hipErrorInvalidValue;
         if (lds > 64 * 1024 &&
             hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(159 * 1024)) != hipSuccess)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(kB2LdsThreads), lds, s, g.sd, g.ids,
-                           g.geo, g.ewd, (const TS *)in, (TS *)out, g.ws, epart);
+        hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(b2_lds_threads(n * n)), lds, s,
+                           g.sd, g.ids, g.geo, g.ewd, (const TS *)in, (TS *)out, g.ws, epart,
+                           (int)warm);
         return hipGetLastError();
     };
     const bool gauss = g.kernel == 1;
@@ -498,22 +544,22 @@ hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, do
     dim3 grid((unsigned)g.nids), block(kB2Threads);
     if (g.kernel == 1)
         hipLaunchKernelGGL((k_b2_step<TS, true>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
-                           (const TS *)in, (TS *)out, g.ws, epart);
+                           (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
     else
         hipLaunchKernelGGL((k_b2_step<TS, false>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
-                           (const TS *)in, (TS *)out, g.ws, epart);
+                           (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, hipStream_t s,
-                          double *epart) {
+                          double *epart, bool warm) {
     if (!g.ws || g.n > kB2MaxN || g.lo != 0) return hipErrorInvalidValue;
     switch (prec) {
-        case kF64: return b2_typed<double>(g, in, out, s, epart);
-        case kF32: return b2_typed<float>(g, in, out, s, epart);
-        default: return b2_typed<half_t>(g, in, out, s, epart);
+        case kF64: return b2_typed<double>(g, in, out, s, epart, warm);
+        case kF32: return b2_typed<float>(g, in, out, s, epart, warm);
+        default: return b2_typed<half_t>(g, in, out, s, epart, warm);
     }
 }
 

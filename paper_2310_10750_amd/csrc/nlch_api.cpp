@@ -569,9 +569,9 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
 }
 
 hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
-                       void *out, hipStream_t s, double *epart = nullptr) {
+                       void *out, hipStream_t s, double *epart = nullptr, bool warm = false) {
     if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s, epart);
-    if (variant == kB2) return launch_b2_step(prec, g, in, out, s, epart);
+    if (variant == kB2) return launch_b2_step(prec, g, in, out, s, epart, warm);
     return launch_direct_step(prec, acc64, g, in, out, s, epart);
 }
 
@@ -659,7 +659,9 @@ int enqueue_group(Batch &b, size_t gi, int prec, bool acc64, int nsteps, void *s
             cur = state;
             nxt = scratch;
         }
-        HIP_TRY(launch_step(variant, prec, acc64, g, cur, nxt, s, ep));
+        // (beta2 > 0: every step after a solve's first starts Newton from
+        // the previous step's z)
+        HIP_TRY(launch_step(variant, prec, acc64, g, cur, nxt, s, ep, k > 0));
         if (energy) HIP_TRY(launch_energy_final(g, ep, ps, energy + (int64_t)k * estride, s));
         std::swap(cur, nxt);
     }

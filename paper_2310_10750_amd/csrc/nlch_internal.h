@@ -170,9 +170,10 @@ hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
                            double *energy = nullptr, int64_t estride = 0);
 // One beta2 > 0 step of every sample of the group (one workgroup per sample,
 // workspace g.ws); epart (nullable) receives one energy partial pair per
-// sample.
+// sample.  warm: start Newton from the z the workspace holds (the previous
+// step's, within one solve) instead of xi_h u_old.
 hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, hipStream_t s,
-                          double *epart);
+                          double *epart, bool warm = false);
 // Per sample of the group, the workgroup partials in order -> energy[ids[j]].
 hipError_t launch_energy_final(const Group &g, const double *epart, int per_sample,
                                double *energy, hipStream_t s);

@@ -102,8 +102,9 @@ def test_b2_trajectory_paper_parameters(orc, prec):
 
 def test_b2_mixed_batch_and_resume(orc):
     """A beta2 > 0 group next to a beta2 = 0 group in one call; each sample
-    equals its own single-sample solve, and a solve split in two calls equals
-    one call (each step starts Newton from the state alone)."""
+    equals its own single-sample solve bit for bit, and a solve split in two
+    calls equals one call to the Newton tolerance (within a call Newton
+    starts from the previous step's z, at a call's first step from xi u)."""
     amp, sigma, _ = synth.gaussian_params(0.25)
     models = [synth.Model(32, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01),
               synth.Model(48, 0.125, 1, amp, sigma, beta2=0.0, tau=0.01)]
@@ -116,7 +117,7 @@ def test_b2_mixed_batch_and_resume(orc):
     c.solve(nsteps=5)
     c.solve(nsteps=7)
     torch.cuda.synchronize()
-    assert torch.equal(a.state, c.state)
+    assert torch.max(torch.abs(a.state - c.state)).item() <= 1e-11
     for k in range(4):
         wk = synth.Workload("one", models, [smp[k]], 12, "f64")
         bk = DeviceBatch(wk)
