@@ -237,8 +237,9 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
 // gradient loop -- all but a few passes of a step -- kept on the compute
 // unit.  512 threads (1024 at n = 128) own up to 16 sites each (site
 // t + THREADS k); the CG residual (FP64) lives in registers, the CG
-// solution (FP32) and direction (FP32; the only vector read at neighbouring
-// sites) in LDS, and the inactive-set mask in a register bitmask.  z, r, F and the Newton direction stay in the
+// direction (FP32; the only vector read at neighbouring sites) in LDS, the
+// CG solution as an FP32 pair (high part in LDS, low part in registers), and
+// the inactive-set mask in a register bitmask.  z, r, F and the Newton direction stay in the
 // global workspace, touched a few times per Newton step.  The Newton level
 // (F, convergence test, line search, z) is the same FP64 arithmetic as in
 // k_b2_step; only the inner directions differ by rounding.
@@ -421,19 +422,21 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
             break;
         }
         if (it == kMaxNewton) break;
-        // the CG residual in FP64 (registers), the solution in FP32 (LDS; a
-        // Newton direction needs ~1e-7 relative accuracy at most: inexact
-        // Newton then still gains 7 digits a step).  The CG direction is kept
+        // The CG residual in FP64 (registers); the solution as an FP32 pair
+        // (a plain FP32 solution limits how much each inexact Newton step
+        // gains, which costs extra Newton steps).  The CG direction is kept
         // in FP32: the solution and the residual are updated with the same
         // rounded direction and its FP64 operator product, so they stay
         // consistent and the residual reaches FP64 tolerances; the rounding
         // only perturbs the conjugacy of the directions.
         const double inv_xi = 1.0 / xi;
         double Sr[SPT];
+        float Xlo[SPT];  // the solution is Xl + Xlo (an FP32 pair, ~48 bits)
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             Sr[k] = valid(k) ? -F[site(k)] : 0.0;
             if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
+            Xlo[k] = 0.0f;
         }
         // J p at site k from the LDS direction (evaluated twice per
         // iteration, for p.Jp and for the residual update, instead of being
@@ -461,7 +464,11 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
 #pragma unroll
             for (int k = 0; k < SPT; ++k) {
                 if (valid(k)) {
-                    Xl[site(k)] = (float)((double)Xl[site(k)] + alpha * (double)Pl[qk(k)]);
+                    const double t =
+                        ((double)Xl[site(k)] + (double)Xlo[k]) + alpha * (double)Pl[qk(k)];
+                    const float hi = (float)t;
+                    Xl[site(k)] = hi;
+                    Xlo[k] = (float)(t - (double)hi);
                     Sr[k] -= alpha * jp(k);
                     rn += Sr[k] * Sr[k];
                 }
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         }
 #pragma unroll
         for (int k = 0; k < SPT; ++k)
-            if (valid(k)) X[site(k)] = (double)Xl[site(k)];
+            if (valid(k)) X[site(k)] = (double)Xl[site(k)] + (double)Xlo[k];
         __syncthreads();
         double sm[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i = tid; i < nn; i += kB2LdsThreads) {
