@@ -208,7 +208,9 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
  * Samples of different models (uneven n and horizon) may be mixed; the
  * library never reorders outputs.  Without NLCH_ALGO_NOGRAPH the sequence of
  * launches is captured once into a HIP graph per distinct call signature
- * (buffers, batch, nsteps, algo) and replayed on later calls.
+ * (buffers, batch, nsteps, algo) and replayed on later calls; a batch keeps
+ * up to 16 graphs (a 17th signature drops them after synchronising the
+ * device).
  * NaN in u0 propagates to the outputs unless NLCH_ALGO_CHECK_FINITE is set. */
 int nlch_solve_batch(const nlch_model *models, int32_t n_models,
                      const nlch_sample *samples, int64_t n_samples,

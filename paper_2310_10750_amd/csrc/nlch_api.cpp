@@ -268,6 +268,7 @@ std::mutex g_mu;
 std::map<int, DevCtx> g_dev;
 std::vector<std::unique_ptr<Batch>> g_batches;  // most recent last
 constexpr size_t kMaxBatches = 32;
+constexpr size_t kMaxGraphsPerBatch = 16;
 
 int dev_ctx(DevCtx **out) {
     int dev = 0;
@@ -837,6 +838,13 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     }
     auto it = b->graphs.find(gk);
     if (it == b->graphs.end()) {
+        if (b->graphs.size() >= kMaxGraphsPerBatch) {
+            // a caller cycling through many buffers or step counts: drop the
+            // cached graphs (after the device has finished any of them)
+            HIP_TRY(hipDeviceSynchronize());
+            for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+            b->graphs.clear();
+        }
         HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
         rc = enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
                            energy_out, n_samples, ctx->capture);

@@ -171,6 +171,23 @@ def test_graph_replay_matches_direct_enqueue():
         assert torch.equal(b.ooi, ref.ooi)
 
 
+def test_graph_cache_eviction_keeps_results():
+    """More distinct call signatures (step counts) than a batch caches graphs
+    for: every call still equals the direct enqueue, also after the cache was
+    dropped, and a repeated signature replays correctly."""
+    w = synth.workload("C1", n_samples=2, nsteps=1, n=64)
+    b = DeviceBatch(w, "f32")
+    ref = DeviceBatch(w, "f32")
+    for k in list(range(1, 21)) + [3, 20]:
+        b.reset()
+        b.solve(nlch.NLCH_ALGO_ROWRUN, nsteps=k)
+        ref.reset()
+        ref.solve(nlch.NLCH_ALGO_ROWRUN | nlch.NLCH_ALGO_NOGRAPH, nsteps=k)
+        torch.cuda.synchronize()
+        assert torch.equal(b.state, ref.state), k
+        assert torch.equal(b.ooi, ref.ooi), k
+
+
 def test_mixed_batch_uneven_sizes(orc):
     """Gaussian kernel, fixed physical horizon, three lattices in one call
     (row-run for 256^2, LDS-resident for 128^2 and 64^2)."""
