@@ -175,11 +175,16 @@ __global__ __launch_bounds__(64) void k_stream(
         gx += gx < 0 ? n : 0;
         gxs[k] = lane + 64 * k < TW ? gx : 0;
     }
+    // rows are fetched two ahead: pre holds the next row to stage, pre2 the
+    // one after (gy is pre2's row)
     int gy = (y0 - M) % n;
     gy += gy < 0 ? n : 0;
-    TS pre[CPL];
+    TS pre[CPL], pre2[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+    gy = gy + 1 < n ? gy + 1 : 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) pre2[k] = src[(int64_t)gy * n + gxs[k]];
 
     const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
@@ -233,10 +238,13 @@ __global__ __launch_bounds__(64) void k_stream(
                 for (int k = 0; k < CPL; ++k)
                     slot[lane + 64 * k] = to_acc<TA>(pre[k]);
                 gy = gy + 1 < n ? gy + 1 : 0;
-                // unconditional (one row past the band at the end; the row
-                // index wraps, so the address stays inside the sample)
+                // unconditional (up to two rows past the band at the end; the
+                // row index wraps, so the address stays inside the sample)
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+                for (int k = 0; k < CPL; ++k) {
+                    pre[k] = pre2[k];
+                    pre2[k] = src[(int64_t)gy * n + gxs[k]];
+                }
                 __syncthreads();  // one wave: makes the staged row visible
                 TA win[WIN];
                 load_window<WIN, (R % 2 == 0)>(slot + c0, win);
@@ -384,11 +392,15 @@ __global__ __launch_bounds__(512) void k_band(
             gx += gx < 0 ? n : 0;
             gxs[k] = lane + 64 * k < TW ? gx : 0;
         }
+        // rows are fetched two ahead (as in k_stream)
         int gy = (y0 - M + s) % n;
         gy += gy < 0 ? n : 0;
-        TS pre[CPL];
+        TS pre[CPL], pre2[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+        gy = gy + 1 < n ? gy + 1 : 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) pre2[k] = src[(int64_t)gy * n + gxs[k]];
         // Centre values are fetched one row ahead of their use, so that the
         // wait before staging a row covers exactly the previous row's loads.
         TS cnext[R];
@@ -421,10 +433,14 @@ __global__ __launch_bounds__(512) void k_band(
 #pragma unroll
                     for (int k = 0; k < CPL; ++k) slot[lane + 64 * k] = to_acc<TA>(pre[k]);
                     gy = gy + 1 < n ? gy + 1 : 0;
-                    // unconditional (one row past the run at the end; the row
-                    // index wraps, so the address stays inside the sample)
+                    // unconditional (up to two rows past the run at the end;
+                    // the row index wraps, so the address stays inside the
+                    // sample)
 #pragma unroll
-                    for (int k = 0; k < CPL; ++k) pre[k] = src[(int64_t)gy * n + gxs[k]];
+                    for (int k = 0; k < CPL; ++k) {
+                        pre[k] = pre2[k];
+                        pre2[k] = src[(int64_t)gy * n + gxs[k]];
+                    }
                     // the ring is private to the wave and LDS operations of
                     // one wave complete in order: only keep the compiler from
                     // reordering the staging stores and the window loads
