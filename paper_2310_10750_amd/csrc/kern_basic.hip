@@ -298,14 +298,18 @@ static hipError_t direct_typed(const Group &g, const void *in, void *out, hipStr
     dim3 grid((unsigned)nb), block(kDirThreads);
     if (g.kernel == 1) {
         auto f = k_direct<TS, TA, true>;
-        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
                            (const TS *)in, (TS *)out, tiles_x, tps, (int)nb, epart);
     } else {
         auto f = k_direct<TS, TA, false>;
-        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL(f, grid, block, lds, s, g.sd, g.ids, g.geo, ew_for<TA>(g),
                            (const TS *)in, (TS *)out, tiles_x, tps, (int)nb, epart);
     }

@@ -90,28 +90,22 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
     auto go = [&](auto f) {
         // per kernel (every instantiation has the same pointer type, so no
         // per-type static flag here)
-        hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kLdsBytes - 1024));
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kLdsBytes - 1024)) != hipSuccess)
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(threads), lds, s, g.sd, g.ids,
                            g.geo, (TS *)state, nsteps, ooi, energy, estride);
+        return hipGetLastError();
     };
-    if (vol) {
-        if (g.ni == 64)
-            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, true>);
-        else
-            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, true>);
-    } else if (energy) {
-        if (g.ni == 64)
-            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>);
-        else
-            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true, false>);
-    } else {
-        if (g.ni == 64)
-            go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, false>);
-        else
-            go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, false>);
-    }
-    return hipGetLastError();
+    if (vol)
+        return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, true>)
+                          : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, true>);
+    if (energy)
+        return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>)
+                          : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true, false>);
+    return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, false>)
+                      : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, false>);
 }
 
 template <class TS, class TA>
