@@ -142,3 +142,26 @@ def test_b2_rejects_nonconvex_steps():
     assert e.value.code == nlch.NLCH_EUNSUPPORTED
     torch.cuda.synchronize()
     assert torch.equal(before, b.state)
+
+
+def test_b2_benchmark_workload_sampled():
+    """The benchmark's beta2 > 0 workload at full size (2048 samples of 128^2,
+    paper parameters, FP32 storage) in its launch configuration, 2 steps:
+    sampled samples against the oracle's trajectory, OoI against each state's
+    mean, every state admissible."""
+    w = synth.workload("B2", nsteps=2)
+    m = w.models[0]
+    b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_AUTO | nlch.NLCH_ALGO_AUTOTUNE)
+    torch.cuda.synchronize()
+    assert torch.all(torch.abs(b.state.float()) <= 1).item()
+    o = b.ooi_host()
+    for i in (0, 1337, 2047):
+        s = w.samples[i]
+        u0 = rounded_initial(w, s, "f32")
+        ref, mean, f1 = b2.solve_b2(u0, w.nsteps, m.n, m.delta, m.kernel, s.amp, m.sigma,
+                                    s.c_F, m.beta1, m.beta2, m.tau)
+        got = b.sample_state(i)
+        assert np.max(np.abs(got - ref)) <= 1e-4, i
+        assert abs(o[i, 1] - f1) <= 1e-6 * abs(f1), i
+        assert abs(o[i, 0] - got.mean()) <= 1e-12, i
