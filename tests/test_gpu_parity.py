@@ -171,6 +171,42 @@ def test_graph_replay_matches_direct_enqueue():
         assert torch.equal(b.ooi, ref.ooi)
 
 
+RESIDENT_R2 = [1, 4, 9, 16, 25, 64]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("R2", RESIDENT_R2)
+def test_resident_one_step_every_disc(orc, R2, n, kind, prec):
+    """Every compiled LDS-resident kernel (disc, lattice, kernel, storage)
+    against the oracle at every site after one and after three steps, from a
+    random admissible state (three samples with their own c_F)."""
+    md = _model(n, R2, kind)
+    algo = nlch.NLCH_ALGO_RESIDENT
+    u = [_rand_state(n, 40 + k, prec) for k in range(3)]
+    host = np.concatenate([v.reshape(-1) for v in u])
+    smp = [nlch.nlch_sample(0, 0, 1.0 + 0.02 * k, md.kernel_amp, k * n * n) for k in range(3)]
+    for nsteps in (1, 3):
+        x = torch.from_numpy(host).to(TDT[prec]).to(DEV)
+        ooi = torch.zeros(6, dtype=torch.float64, device=DEV)
+        try:
+            nlch.nlch_solve_batch([md], smp, nsteps, nlch.PRECISIONS[prec], algo, x, None, ooi)
+        except nlch.NlchError as e:
+            assert e.code == nlch.NLCH_EUNSUPPORTED
+            pytest.skip("no resident kernel for n=%d R2=%d at %s" % (n, R2, prec))
+        torch.cuda.synchronize()
+        got = x.double().cpu().numpy().reshape(3, n, n)
+        for k in range(3):
+            ref = u[k]
+            for _ in range(nsteps):
+                ref = orc.step(ref, n, md.delta, md.kernel, md.kernel_amp, md.kernel_sigma,
+                               smp[k].c_F, md.beta1, md.tau)
+            tol = ONE_STEP_TOL[prec] * (1 if nsteps == 1 else 10)
+            assert np.max(np.abs(got[k] - ref)) <= tol, (k, nsteps)
+            assert abs(ooi.cpu().numpy()[2 * k] - got[k].mean()) <= 1e-12
+
+
 def test_graph_cache_eviction_keeps_results():
     """More distinct call signatures (step counts) than a batch caches graphs
     for: every call still equals the direct enqueue, also after the cache was
