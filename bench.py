@@ -114,10 +114,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU only: every box of this pool has one "
-              "MI355X, and the solver runs no multi-GPU path (samples would shard "
-              "by sample index with one FP64 all-reduce of the moment sums).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(samples would shard by sample index, with one FP64 all-reduce of "
+              "the moment sums).", file=sys.stderr)
         sys.exit(2)
 
     import torch
