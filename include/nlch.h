@@ -314,7 +314,8 @@ int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap);
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *nlch_last_error(void);
 
-/* ABI version (increments on any change to this header). */
+/* ABI version: 4 (increments on any change to a struct, constant or function
+ * signature declared here). */
 int nlch_version(void);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
             "nlch_version"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert nlch.nlch_version() >= 1
+    assert nlch.nlch_version() == 4
 
 
 def test_struct_layouts_match_header():
