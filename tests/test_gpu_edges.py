@@ -1,8 +1,8 @@
 """GPU edge cases against the FP64 oracle, through the C ABI: the degenerate
 horizon delta = 0 (the disc is the site itself, so the nonlocal operator
 vanishes), the widest horizon the direct kernel takes (m = 48), the smallest
-lattices a disc allows (n = 2m + 1), and a solve of zero steps (projection and
-output of interest only)."""
+lattices a disc allows (n = 2m + 1), a solve of zero steps (projection and
+output of interest only), and a lattice whose indices pass 2^31 bytes."""
 import math
 
 import numpy as np
@@ -107,3 +107,29 @@ def test_zero_steps_projects_and_reduces(algo, prec):
     o = ooi.cpu().numpy()
     assert abs(o[0] - got.mean()) <= 1e-13
     assert abs(o[1] - 0.5 * (1 + got.mean())) <= 1e-13
+
+
+@pytest.mark.parametrize("algo", ["rowrun", "direct"])
+def test_large_lattice_indexing(orc, algo):
+    """A 20000^2 lattice (4e8 sites, 1.6 GB per FP32 state; offsets past 2^31
+    bytes and 2^28 elements): one step at sampled sites, including the last
+    rows and columns, against the oracle evaluated at those sites."""
+    n = 20000
+    md = _model(n, 64, 0)
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-0.9, 0.9, n * n).astype(np.float32)
+    x = torch.from_numpy(u).to(DEV)
+    y = torch.empty_like(x)
+    ooi = torch.zeros(2, dtype=torch.float64, device=DEV)
+    nlch.nlch_step(md, nlch.NLCH_F32, A[algo], x, y, ooi)
+    torch.cuda.synchronize()
+    sites = np.concatenate([[0, n - 1, n * n - n, n * n - 1, (n // 2) * n + n // 2],
+                            rng.integers(0, n * n, 2000)])
+    got = y[torch.from_numpy(sites).to(DEV)].double().cpu().numpy()
+    ref = orc.step_sites(u.astype(np.float64).reshape(n, n), sites, n, md.delta, md.kernel,
+                         md.kernel_amp, md.kernel_sigma, md.c_F, md.beta1, md.tau)
+    assert np.max(np.abs(got - ref)) <= TOL["f32"]
+    mean = float(y.double().mean().item())
+    assert abs(ooi.cpu().numpy()[0] - mean) <= 1e-12
+    del x, y
+    torch.cuda.empty_cache()
