@@ -153,32 +153,38 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
         rr += r * r;
     }
     const double scale = fmax(1.0, sqrt(block_sum1(rr, red)));
+    // inverse diagonal of J (Jacobi preconditioner): active and inactive sites
+    const double d_act = 1.0 / (tb1 + 4.0 * tb2n2), d_ina = 1.0 / (tb1 + 4.0 * tb2n2 + 1.0 / xi);
 
     bool ok = false;
     for (int it = 0;; ++it) {
         // F(z); converged when |F| <= 1e-13 max(1, |r|)
-        double f2 = 0.0;
+        double f2r[2] = {0.0, 0.0};  // |F|^2 and F.M^-1 F
         for (int i = tid; i < nn; i += kB2Threads) {
             const int y = i / n, x = i - y * n;
             const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(Z[i] / xi) - R[i];
+            const double dv = fabs(Z[i]) < xi ? d_ina : d_act;
             F[i] = f;
             X[i] = 0.0;
             S[i] = -f;
-            P[i] = -f;
-            f2 += f * f;
+            P[i] = -f * dv;
+            f2r[0] += f * f;
+            f2r[1] += f * (f * dv);
         }
-        f2 = block_sum1(f2, red);
+        block_sums<2>(f2r, red);
+        const double f2 = f2r[0];
         if (sqrt(f2) <= 1e-13 * scale) {
             ok = true;
             break;
         }
         if (it == kMaxNewton) break;
-        // conjugate gradients on J x = -F (x0 = 0), relative tolerance
-        // min(1e-2, |F| / scale) (inexact Newton: superlinear near the root)
+        // Jacobi-preconditioned conjugate gradients on J x = -F (x0 = 0),
+        // relative tolerance min(1e-2, |F| / scale) in the norm s.M^-1 s of
+        // the residual (inexact Newton: superlinear near the root)
         const double eta = fmin(1e-2, sqrt(f2) / scale);
-        const double stop = eta * eta * f2;
-        double rs = f2;
-        for (int k = 0; k < kMaxCg && rs > stop; ++k) {
+        const double stop = eta * eta * f2r[1];
+        double rz = f2r[1];
+        for (int k = 0; k < kMaxCg && rz > stop; ++k) {
             double pq = 0.0;
             for (int i = tid; i < nn; i += kB2Threads) {
                 const int y = i / n, x = i - y * n;
@@ -189,18 +195,19 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
             }
             pq = block_sum1(pq, red);
             if (!(pq > 0.0)) break;
-            const double alpha = rs / pq;
-            double rn = 0.0;
+            const double alpha = rz / pq;
+            double rn = 0.0;  // s.M^-1 s
             for (int i = tid; i < nn; i += kB2Threads) {
                 X[i] += alpha * P[i];
                 const double sv = S[i] - alpha * Q[i];
                 S[i] = sv;
-                rn += sv * sv;
+                rn += sv * (sv * (fabs(Z[i]) < xi ? d_ina : d_act));
             }
             rn = block_sum1(rn, red);
-            const double beta = rn / rs;
-            rs = rn;
-            for (int i = tid; i < nn; i += kB2Threads) P[i] = S[i] + beta * P[i];
+            const double beta = rn / rz;
+            rz = rn;
+            for (int i = tid; i < nn; i += kB2Threads)
+                P[i] = S[i] * (fabs(Z[i]) < xi ? d_ina : d_act) + beta * P[i];
             __syncthreads();
         }
         // Armijo backtracking on Phi along x:
@@ -248,14 +255,52 @@ constexpr int b2_lds_threads(int nn) { return nn >= 128 * 128 ? 1024 : 512; }
 constexpr int kB2LdsMaxWaves = 16;
 constexpr int kB2Spt = 16;  // sites per thread
 
+// One FP64 value moved between lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// A value that every lane holds alike, moved to scalar registers (the
+// kernel's vector registers are its limit).
+__device__ __forceinline__ double uniform_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave-wide FP64 sum in a fixed order, returned to every lane: pairs, quads,
+// half rows and rows of 16 lanes by DPP exchanges (each step adds two
+// partial sums that both partners hold, so a row ends with one value in all
+// its lanes), then the four rows as (r0 + r1) + (r2 + r3).  No LDS traffic
+// and no lane-address registers, unlike a shuffle tree.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) +
+           (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Workgroup sums with one barrier: successive calls must alternate between
 // two `red` areas (a thread writes area A for sum k + 2 only after the
 // barrier of sum k + 1, which every thread passes after reading sum k).
 template <int K, int WAVES>
 __device__ __forceinline__ void block_sums_lds(double (&v)[K], double *red) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_f64(v[k]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -398,10 +443,13 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         if (y == n - 1) Pl[q - n * W] = v;
     };
 
+    // inverse diagonal of J (Jacobi preconditioner): active and inactive sites
+    const double d_act = uniform_f64(1.0 / (tb1 + 4.0 * tb2n2)),
+                 d_ina = uniform_f64(1.0 / (tb1 + 4.0 * tb2n2 + 1.0 / xi));
     bool ok = false;
     for (int it = 0;; ++it) {
-        // F(z), the CG start (direction -F, to LDS) and the inactive-set mask
-        double f2 = 0.0;
+        // F(z), the CG start (direction -M^-1 F, to LDS) and the inactive-set mask
+        double f2r[2] = {0.0, 0.0};  // |F|^2 and F.M^-1 F
         unsigned mask = 0;  // bit k: site t + THREADS k inactive (|z| < xi)
 #pragma unroll 1
         for (int k = 0; k < SPT; ++k) {
@@ -410,13 +458,17 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
                 const int y = i / n, x = i - y * n;
                 const double zi = Z[i];
                 const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(zi / xi) - R[i];
+                const bool ina = fabs(zi) < xi;
+                const double dv = ina ? d_ina : d_act;
                 F[i] = f;
-                put(k, -f);
-                if (fabs(zi) < xi) mask |= 1u << k;
-                f2 += f * f;
+                put(k, -f * dv);
+                if (ina) mask |= 1u << k;
+                f2r[0] += f * f;
+                f2r[1] += f * (f * dv);
             }
         }
-        f2 = sum1_lds<kB2LdsWaves>(f2, red());  // also makes Pl visible
+        block_sums_lds<2, kB2LdsWaves>(f2r, red());  // also makes Pl visible
+        const double f2 = f2r[0];
         if (sqrt(f2) <= 1e-13 * scale) {
             ok = true;
             break;
@@ -429,7 +481,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         // rounded direction and its FP64 operator product, so they stay
         // consistent and the residual reaches FP64 tolerances; the rounding
         // only perturbs the conjugacy of the directions.
-        const double inv_xi = 1.0 / xi;
+        const double inv_xi = uniform_f64(1.0 / xi);
         double Sr[SPT];
         float Xlo[SPT];  // the solution is Xl + Xlo (an FP32 pair, ~48 bits)
 #pragma unroll
@@ -438,47 +490,85 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
             if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
             Xlo[k] = 0.0f;
         }
-        // J p at site k from the LDS direction (evaluated twice per
-        // iteration, for p.Jp and for the residual update, instead of being
-        // kept in registers)
-        auto jp = [&](int k) {
-            const int q = qk(k);
-            const double pi = Pl[q];
-            const double ap = tb1 * pi - tb2n2 * ((double)Pl[q + 1] + (double)Pl[q - 1] +
-                                                  (double)Pl[q + W] + (double)Pl[q - W] -
-                                                  4.0 * pi);
-            return ap + ((mask >> k) & 1u ? pi * inv_xi : 0.0);
-        };
         const double eta = fmin(1e-2, sqrt(f2) / scale);
-        const double stop = eta * eta * f2;
-        double rs = f2;
-        for (int kk = 0; kk < kMaxCg && rs > stop; ++kk) {
+        const double stop = eta * eta * f2r[1];
+        double rz = f2r[1];
+        for (int kk = 0; kk < kMaxCg && rz > stop; ++kk) {
+            // the per-site selections of the preconditioner are made in
+            // every iteration: an empty asm statement hides the two values
+            // from the optimiser, which would otherwise hoist 16 selected
+            // FP64 values (32 registers) out of the loop and spill them
+            double da = d_act, di = d_ina;
+            __asm__ volatile("" : "+v"(da), "+v"(di));
+            auto dinv = [&](int k) { return (mask >> k) & 1u ? di : da; };
+            // J p at site k from the direction's five LDS values (evaluated
+            // twice per iteration, for p.Jp and for the residual update,
+            // instead of being kept in registers).  Where the sites sit at
+            // fixed offsets (n = 64, 128), each site's values are loaded
+            // while the previous site is computed (elsewhere that costs
+            // spills); the scheduling barriers keep the sites in that order.
+            struct Nb {
+                float c, e, w, n, s;
+            };
+            auto ld = [&](int k) {
+                Nb v{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (valid(k)) {
+                    const int q = qk(k);
+                    v = Nb{Pl[q], Pl[q + 1], Pl[q - 1], Pl[q + W], Pl[q - W]};
+                }
+                return v;
+            };
+            auto jp = [&](int k, const Nb &v) {
+                const double pi = v.c;
+                const double ap = tb1 * pi - tb2n2 * ((double)v.e + (double)v.w + (double)v.n +
+                                                      (double)v.s - 4.0 * pi);
+                return ap + ((mask >> k) & 1u ? pi * inv_xi : 0.0);
+            };
             double pq = 0.0;
+            {
+                Nb nxt = EXACT ? ld(0) : Nb{};
 #pragma unroll
-            for (int k = 0; k < SPT; ++k)
-                if (valid(k)) pq += (double)Pl[qk(k)] * jp(k);
+                for (int k = 0; k < SPT; ++k) {
+                    const Nb cur = EXACT ? nxt : ld(k);
+                    if (EXACT && k + 1 < SPT) nxt = ld(k + 1);
+                    if (valid(k)) pq += (double)cur.c * jp(k, cur);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
             pq = sum1_lds<kB2LdsWaves>(pq, red());
             if (!(pq > 0.0)) break;
-            const double alpha = rs / pq;
-            double rn = 0.0;
+            const double alpha = uniform_f64(rz / pq);
+            double rn = 0.0;  // s.M^-1 s
+            {
+                Nb nxt = EXACT ? ld(0) : Nb{};
+                float xnxt = EXACT ? Xl[site(0)] : 0.0f;
 #pragma unroll
-            for (int k = 0; k < SPT; ++k) {
-                if (valid(k)) {
-                    const double t =
-                        ((double)Xl[site(k)] + (double)Xlo[k]) + alpha * (double)Pl[qk(k)];
-                    const float hi = (float)t;
-                    Xl[site(k)] = hi;
-                    Xlo[k] = (float)(t - (double)hi);
-                    Sr[k] -= alpha * jp(k);
-                    rn += Sr[k] * Sr[k];
+                for (int k = 0; k < SPT; ++k) {
+                    const Nb cur = EXACT ? nxt : ld(k);
+                    const float xc = EXACT ? xnxt : (valid(k) ? Xl[site(k)] : 0.0f);
+                    if (EXACT && k + 1 < SPT) {
+                        nxt = ld(k + 1);
+                        xnxt = Xl[site(k + 1)];
+                    }
+                    if (valid(k)) {
+                        const double t = ((double)xc + (double)Xlo[k]) + alpha * (double)cur.c;
+                        const float hi = (float)t;
+                        Xl[site(k)] = hi;
+                        Xlo[k] = (float)(t - (double)hi);
+                        Sr[k] -= alpha * jp(k, cur);
+                        rn += Sr[k] * (Sr[k] * dinv(k));
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             rn = sum1_lds<kB2LdsWaves>(rn, red());  // every thread has read Pl before it changes
-            const double beta = rn / rs;
-            rs = rn;
+            const double beta = uniform_f64(rn / rz);
+            rz = rn;
 #pragma unroll
-            for (int k = 0; k < SPT; ++k)
-                if (valid(k)) put(k, Sr[k] + beta * (double)Pl[qk(k)]);
+            for (int k = 0; k < SPT; ++k) {
+                if (valid(k)) put(k, Sr[k] * dinv(k) + beta * (double)Pl[qk(k)]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
             __syncthreads();
         }
 #pragma unroll
