@@ -75,8 +75,8 @@ def algorithmic_ops(m: int, kernel: int) -> int:
     return 2 * m + (2 * m + 1) + 6
 
 
-def stored_traffic(kernel_name: str, workload: str):
-    """HBM bytes per launch of the kernel from the committed counter summary,
+def stored_counters(kernel_name: str, workload: str):
+    """The committed counter summary of the kernel (profiles/traffic.json),
     if it was measured on this workload and on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
@@ -90,7 +90,14 @@ def stored_traffic(kernel_name: str, workload: str):
         return None
     if not e.get("workload", "").startswith(workload + ":"):
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def stored_traffic(kernel_name: str, workload: str):
+    """HBM bytes per launch of the kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None."""
+    e = stored_counters(kernel_name, workload)
+    return e.get("bytes_per_launch") if e else None
 
 
 def main():
@@ -212,6 +219,14 @@ def main():
         roofline = None
     state_bytes = total * np.dtype(ndt).itemsize
     hbm_gbs = 2 * state_bytes / (solve_ms * 1e-3) / 1e9
+    # LDS bytes per launch from the committed counters (SQ_INSTS_LDS_LOAD- and
+    # _STORE_BANDWIDTH, 64-byte units), over this run's launch duration
+    ctr = stored_counters(kname, w.name)
+    lds = None
+    if ctr and ctr.get("lds_bytes_per_launch") and roofline is not None:
+        lb = ctr["lds_bytes_per_launch"]
+        lds = {"bytes_per_launch": lb, "bytes_per_site_step": round(lb / site_steps, 2),
+               "achieved_gbs": round(lb / (solve_ms * 1e-3) / 1e9, 1)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1,
@@ -223,6 +238,7 @@ def main():
                    "time_steps": w.nsteps, "precision": prec, "algo": args.algo},
         "roofline": roofline,
         "hbm_state_gbs": round(hbm_gbs, 1),
+        "lds": lds,
     }
     if est is not None:
         out["mfmc_estimate"] = {"q_mfmc": est["q_mfmc"], "q_mc": est["q_mc"],

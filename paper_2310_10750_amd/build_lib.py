@@ -55,9 +55,27 @@ def _stale(src):
     return max(os.path.getmtime(f) for f in deps) > os.path.getmtime(obj)
 
 
+PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
+PEAKS = os.path.join(HERE, "peaks", "nlch_peaks")
+
+
+def build_peaks(verbose: bool = True) -> str:
+    """Compiles the peak-measurement program (HBM copy, LDS read, FP32/FP64
+    issue rates) with the library's flags."""
+    t0 = time.time()
+    cmd = [HIPCC] + [f for f in COMMON if f != "-fPIC"] + [PEAKS_SRC, "-o", PEAKS]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed on peaks.hip:\n" + r.stdout + r.stderr)
+    if verbose:
+        print("  hipcc %-28s %6.1fs" % ("peaks/peaks.hip", time.time() - t0), flush=True)
+    return PEAKS
+
+
 def build(verbose: bool = True, jobs: int = None, incremental: bool = False) -> str:
     """Compiles every unit (or, with incremental, only those whose object is
-    older than its sources) and links the library."""
+    older than its sources) and links the library; also builds the
+    peak-measurement program."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     todo = [s for s in srcs if _stale(s)] if incremental else srcs
@@ -75,6 +93,9 @@ def build(verbose: bool = True, jobs: int = None, incremental: bool = False) -> 
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    if not incremental or not os.path.exists(PEAKS) or (
+            os.path.getmtime(PEAKS_SRC) > os.path.getmtime(PEAKS)):
+        build_peaks(verbose)
     return LIB
 
 

@@ -1,0 +1,72 @@
+"""Host logic of bench.py: the algorithmic operation count behind the
+roofline, the hash that ties stored counter data to the kernel sources they
+were measured on, the stored counter summary itself, and the refusal of more
+than one GPU."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("m,ops", [(0, 7), (1, 11), (8, 39), (32, 135)])
+def test_algorithmic_ops_is_4m_plus_7(m, ops):
+    # 2m window terms, 2m+1 row sums, 6 for the update and projection
+    assert bench.algorithmic_ops(m, 0) == ops
+    assert bench.algorithmic_ops(m, 1) == ops
+
+
+def test_source_hash_tracks_the_kernel_sources(tmp_path, monkeypatch):
+    h = bench.kernel_source_hash("k_resident")
+    assert len(h) == 16 and int(h, 16) >= 0
+    assert bench.kernel_source_hash("k_resident") == h
+    # a copy of the sources with one byte changed hashes differently
+    csrc = os.path.join(ROOT, "paper_2310_10750_amd", "csrc")
+    fake = tmp_path / "paper_2310_10750_amd" / "csrc"
+    fake.mkdir(parents=True)
+    for f in bench.KERNEL_SOURCES["k_resident"]:
+        data = open(os.path.join(csrc, f), "rb").read()
+        if f == "kern_rowrun_impl.h":
+            data += b"\n"
+        (fake / f).write_bytes(data)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_source_hash("k_resident") != h
+
+
+def test_stored_counters_are_consistent():
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    e = d["k_resident"]
+    assert e["bytes_per_launch"] == pytest.approx(e["fetch_bytes"] + e["write_bytes"], abs=2)
+    assert e["algorithmic_bytes"] == 2 * 4096 * 128 * 128 * 4
+    # HBM: within a few percent of reading and writing each state once
+    assert 0.99 < e["bytes_per_launch"] / e["algorithmic_bytes"] < 1.05
+    if "lds_bytes_per_launch" in e:
+        assert e["lds_bytes_per_launch"] == e["lds_load_bytes"] + e["lds_store_bytes"]
+
+
+def test_stored_counters_only_for_their_workload_and_sources(monkeypatch):
+    e = bench.stored_counters("k_resident", "C3")
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_resident"]
+    if d["source_hash"] == bench.kernel_source_hash("k_resident"):
+        assert e is not None and e["bytes_per_launch"] == d["bytes_per_launch"]
+        assert bench.stored_traffic("k_resident", "C3") == d["bytes_per_launch"]
+    else:
+        assert e is None
+    assert bench.stored_counters("k_resident", "V3") is None
+    assert bench.stored_counters("k_rowrun", "C3") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k="k_resident": "0" * 16)
+    assert bench.stored_counters("k_resident", "C3") is None
+    assert bench.stored_traffic("k_resident", "C3") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
