@@ -100,6 +100,25 @@ def stored_traffic(kernel_name: str, workload: str):
     return e.get("bytes_per_launch") if e else None
 
 
+def host_info():
+    """The CPU the oracle baseline ran on: model name, logical CPUs, and the
+    CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,7 +344,8 @@ def main():
                                "cores": cores, "kind": "oracle",
                                "sample": "samples 0..%d of %d, all %d steps each "
                                          "(%.1f s of oracle time)"
-                                         % (k - 1, S, w.nsteps, tcpu)}
+                                         % (k - 1, S, w.nsteps, tcpu),
+                               "host": host_info()}
         out["ooi_rel_err"] = {"max": max(rel), "samples": k, "vs": "FP64 CPU oracle"}
         log("cpu oracle %.3e site-steps/s on %d threads; max OoI rel err %.2e"
             % (sscpu / tcpu, cores, max(rel)))

@@ -70,3 +70,9 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_host_info_names_the_cpu():
+    h = bench.host_info()
+    assert h["logical_cpus"] == os.cpu_count()
+    assert h["usable_cpus"] is None or 1 <= h["usable_cpus"] <= h["logical_cpus"]
