@@ -165,3 +165,35 @@ def test_b2_benchmark_workload_sampled():
         assert np.max(np.abs(got - ref)) <= 1e-4, i
         assert abs(o[i, 1] - f1) <= 1e-6 * abs(f1), i
         assert abs(o[i, 0] - got.mean()) <= 1e-12, i
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [64, 128, 40])
+def test_b2_all_active_and_all_inactive_states(orc, n, prec):
+    """The two extremes of the active set, on the on-chip (64^2, 128^2) and
+    the workspace (40^2) kernels: u = +-1 everywhere (every site at the
+    obstacle: the Newton system is tau A alone) is stationary and u = 0
+    stationary; a small cosine mode (no site near the obstacle: every site
+    inactive) advances by the linear step, against the oracle."""
+    print("b2 extremes n=%d %s" % (n, prec), flush=True)
+    delta = 8.0 / n if n >= 64 else 4.0 / n
+    sigma = delta / 3
+    amp = _amp_for(orc, n, delta, 1, sigma, 0.0253)
+    md = nlch.make_model(n, delta, 1, amp, sigma, c_F=1.0, beta1=1.0, beta2=0.05, tau=0.01)
+
+    def step(u):
+        x = torch.from_numpy(u.reshape(-1)).to(TDT[prec]).to(DEV)
+        y = torch.empty_like(x)
+        nlch.nlch_step(md, nlch.PRECISIONS[prec], nlch.NLCH_ALGO_AUTO, x, y, None)
+        torch.cuda.synchronize()
+        return y.double().cpu().numpy().reshape(n, n)
+
+    for c in (1.0, -1.0, 0.0):
+        assert np.all(step(np.full((n, n), c)) == c), c
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    u = 1e-3 * np.cos(2 * np.pi * (3 * xx + 2 * yy) / n)
+    u = u.astype(NPD[prec]).astype(np.float64)
+    got = step(u)
+    ref, _, _ = b2.step_b2(u, n, delta, 1, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+    assert np.max(np.abs(got - ref)) <= (1e-11 if prec == "f64" else 1e-9)
+    assert np.max(np.abs(ref)) < 0.01  # nowhere near the obstacle
