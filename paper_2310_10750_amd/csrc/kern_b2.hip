@@ -252,6 +252,15 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
 // k_b2_step; only the inner directions differ by rounding.
 // Workgroup size: 1024 threads (16 sites each) from n = 128 on, else 512.
 constexpr int b2_lds_threads(int nn) { return nn >= 128 * 128 ? 1024 : 512; }
+constexpr size_t kB2LdsLimit = 159 * 1024;
+
+// Whether the g pass's copy of u with a periodic halo of m on every side
+// (elements of tu bytes; side n + 2m) fits in LDS with the weight table:
+// the kernel and its launch decide alike.
+__host__ __device__ constexpr bool b2_padded_fits(int n, int m, int tu) {
+    return tu == 4 && (size_t)tu * (n + 2 * m) * (n + 2 * m) +
+                              sizeof(double) * (size_t)(m + 1) * (m + 1) <= kB2LdsLimit;
+}
 constexpr int kB2LdsMaxWaves = 16;
 constexpr int kB2Spt = 16;  // sites per thread
 
@@ -356,11 +365,24 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
 
     // g and the energy partials of u_old, from copies of u_old (exact: FP64
     // for FP64 storage, else FP32) and of the weight table in LDS, which the
-    // CG direction reuses afterwards
+    // CG direction reuses afterwards.  Where it fits (FP32 copies), the copy
+    // carries a periodic halo of m on every side, so that the disc rows are
+    // read without wrapping and the two points at -dx and +dx, which share
+    // a weight, are added before it multiplies them.
     using TU = typename std::conditional<std::is_same<TS, double>::value, double, float>::type;
+    const bool padded = b2_padded_fits(n, m, (int)sizeof(TU));
+    const int S = n + 2 * m;  // side of the padded copy
     TU *Ul = reinterpret_cast<TU *>(smem_raw);
-    double *El = reinterpret_cast<double *>(smem_raw + sizeof(TU) * nn);
-    for (int i = tid; i < nn; i += kB2LdsThreads) Ul[i] = (TU)(double)u[i];
+    double *El = reinterpret_cast<double *>(
+        smem_raw + sizeof(TU) * (padded ? (size_t)S * S : (size_t)nn));
+    if (padded) {
+        for (int i = tid; i < S * S; i += kB2LdsThreads) {
+            const int Y = i / S, X = i - Y * S;
+            Ul[i] = (TU)(double)u[wrap_once(Y - m, n) * n + wrap_once(X - m, n)];
+        }
+    } else {
+        for (int i = tid; i < nn; i += kB2LdsThreads) Ul[i] = (TU)(double)u[i];
+    }
     if (GAUSS)
         for (int i = tid; i < (m + 1) * (m + 1); i += kB2LdsThreads) El[i] = e[i];
     __syncthreads();
@@ -369,18 +391,39 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         constexpr bool EN_ = decltype(EN)::value;  // with the energy partials
         for (int i = tid; i < nn; i += kB2LdsThreads) {
             const int y = i / n, x = i - y * n;
-            const double ui = (double)Ul[i];
-            double acc = 0.0, lsum = 0.0;
-            for (int dy = -m; dy <= m; ++dy) {
-                const int ady = dy < 0 ? -dy : dy;
-                const int w = geo->halfw[ady];
-                const TU *row = Ul + wrap_once(y + dy, n) * n;
-                const double *er = El + ady * (m + 1);
-                for (int dx = -w; dx <= w; ++dx) {
-                    const double v = (double)row[wrap_once(x + dx, n)];
-                    const double wt = GAUSS ? er[dx < 0 ? -dx : dx] : 1.0;
-                    acc += wt * v;
-                    if (EN_) lsum += wt * (ui - v);
+            double acc = 0.0, lsum = 0.0, ui;
+            if (padded) {
+                const TU *c = Ul + (y + m) * S + (x + m);
+                ui = (double)c[0];
+                for (int dy = -m; dy <= m; ++dy) {
+                    const int ady = dy < 0 ? -dy : dy;
+                    const int w = geo->halfw[ady];
+                    const TU *row = c + dy * S;
+                    const double *er = El + ady * (m + 1);
+                    const double v0 = (double)row[0];
+                    const double w0 = GAUSS ? er[0] : 1.0;
+                    acc += w0 * v0;
+                    if (EN_) lsum += w0 * (ui - v0);
+                    for (int k = 1; k <= w; ++k) {
+                        const double pr = (double)row[-k] + (double)row[k];
+                        const double wk = GAUSS ? er[k] : 1.0;
+                        acc += wk * pr;
+                        if (EN_) lsum += wk * (2.0 * ui - pr);
+                    }
+                }
+            } else {
+                ui = (double)Ul[i];
+                for (int dy = -m; dy <= m; ++dy) {
+                    const int ady = dy < 0 ? -dy : dy;
+                    const int w = geo->halfw[ady];
+                    const TU *row = Ul + wrap_once(y + dy, n) * n;
+                    const double *er = El + ady * (m + 1);
+                    for (int dx = -w; dx <= w; ++dx) {
+                        const double v = (double)row[wrap_once(x + dx, n)];
+                        const double wt = GAUSS ? er[dx < 0 ? -dx : dx] : 1.0;
+                        acc += wt * v;
+                        if (EN_) lsum += wt * (ui - v);
+                    }
                 }
             }
             G[i] = gs * acc;
@@ -608,16 +651,17 @@ hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, do
                     bool warm) {
     // on-chip variant for the lattices of the multifidelity study
     auto lds_launch = [&](auto f, int n) {
-        // the CG direction and solution (FP32), or, before them, u_old and
-        // the weight table
+        // the CG direction and solution (FP32), or, before them, u_old (with
+        // its halo where that fits) and the weight table
+        const int tu = std::is_same<TS, double>::value ? 8 : 4;
+        const size_t side = b2_padded_fits(n, g.m, tu) ? (size_t)(n + 2 * g.m) : (size_t)n;
         const size_t lds = std::max(
             sizeof(float) * ((size_t)(n + 2) * (n + 2) + (size_t)n * n),
-            (std::is_same<TS, double>::value ? 8 : 4) * (size_t)n * n +
-                sizeof(double) * (size_t)(g.m + 1) * (g.m + 1));
-        if (lds > 159 * 1024) return hipErrorInvalidValue;
+            tu * side * side + sizeof(double) * (size_t)(g.m + 1) * (g.m + 1));
+        if (lds > kB2LdsLimit) return hipErrorInvalidValue;
         if (lds > 64 * 1024 &&
             hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(159 * 1024)) != hipSuccess)
+                                (int)kB2LdsLimit) != hipSuccess)
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(b2_lds_threads(n * n)), lds, s,
                            g.sd, g.ids, g.geo, g.ewd, (const TS *)in, (TS *)out, g.ws, epart,
