@@ -27,8 +27,8 @@
  *     mu in the normal cone of [-1, 1]^{n^2} at u,
  * which for xi_h > 0 has a unique solution: with z = xi_h u + mu,
  * u = clamp(z / xi_h) and z is the root of a strictly convex gradient, found
- * by semismooth Newton with conjugate-gradient inner solves (FP64, one
- * workgroup per sample, n <= 256).  Models with beta2 > 0 and a sample with
+ * by semismooth Newton with Jacobi-preconditioned conjugate-gradient inner
+ * solves (FP64, one workgroup per sample, n <= 256).  Models with beta2 > 0 and a sample with
  * xi_h <= 0 (a non-convex step with possibly several solutions) are
  * NLCH_EUNSUPPORTED.  A sample whose Newton iteration does not converge
  * within its iteration cap gets a NaN state and output of interest.
