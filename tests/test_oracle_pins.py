@@ -346,3 +346,53 @@ def test_rejects_unstable_denominator(orc):
         orc.step(np.zeros((n, n)), n, 2 / n, 0, 1.0, 0.0, 500.0, 1.0, 1.0)
     with pytest.raises(Exception):
         orc.step(np.zeros((n, n)), n, 8 / n, 0, 1.0, 0.0, 1.0, 1.0, 0.01)
+
+
+# ------------------------------------------------ per-site step -----------
+
+def _edge_sites(n):
+    """Flat indices of the four corners, a site on each edge, the sites next
+    to the corners and the centre of an n x n lattice."""
+    pts = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1),
+           (0, n // 2), (n - 1, n // 3), (n // 2, 0), (n // 3, n - 1),
+           (1, 1), (1, n - 2), (n - 2, 1), (n - 2, n - 2), (n // 2, n // 2)]
+    return np.array([y * n + x for y, x in pts], dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,r2,kind", [(12, 4, 0), (16, 10, 1), (23, 16, 0),
+                                       (24, 25, 1), (40, 64, 0), (41, 81, 1)])
+def test_step_sites_matches_full_step_and_dense_step(orc, n, r2, kind):
+    """One step evaluated at chosen sites equals the whole-lattice step there
+    bit for bit, and equals the dense implicit-Euler step (the minimum-image
+    operator built from all node pairs, then the projection) to rounding: at
+    random interior sites, the four corners, every edge and the sites next to
+    the corners, where the disc wraps around the torus."""
+    delta = math.sqrt(r2) / n
+    amp, sigma = (1.0253 * n * n / 49.0, 0.0) if kind == 0 else (2500.0, 0.04)
+    c_F, beta1, tau = 0.95, 1.0, 0.05
+    rng = np.random.default_rng(n * 100 + r2)
+    u = np.clip(rng.uniform(-1.2, 1.2, (n, n)), -1, 1)
+    sites = np.concatenate([_edge_sites(n),
+                            rng.choice(n * n, size=min(40, n * n), replace=False)])
+    got = orc.step_sites(u, sites, n, delta, kind, amp, sigma, c_F, beta1, tau)
+    full = orc.step(u, n, delta, kind, amp, sigma, c_F, beta1, tau).reshape(-1)
+    assert np.array_equal(got, full[sites])
+    W = _dense_operator(n, delta, kind, amp, sigma)
+    cg = W[0].sum()
+    tb = tau * beta1
+    dense = np.clip((u.reshape(-1) + tb * (W @ u.reshape(-1))) / (1 + tb * (cg - c_F)),
+                    -1, 1)
+    assert np.max(np.abs(got - dense[sites])) < 1e-13
+    # the sites are evaluated independently: order and repeats do not matter
+    perm = np.concatenate([sites[::-1], sites[:3]])
+    got2 = orc.step_sites(u, perm, n, delta, kind, amp, sigma, c_F, beta1, tau)
+    assert np.array_equal(got2, full[perm])
+
+
+def test_step_sites_rejects_out_of_range_sites(orc):
+    n = 16
+    u = np.zeros((n, n))
+    for bad in ([-1], [n * n], [0, n * n + 5]):
+        with pytest.raises(Exception):
+            orc.step_sites(u, np.array(bad, dtype=np.int64), n, 2 / n, 0, 1.0, 0.0,
+                           1.0, 1.0, 0.01)
