@@ -28,7 +28,9 @@
  * which for xi_h > 0 has a unique solution: with z = xi_h u + mu,
  * u = clamp(z / xi_h) and z is the root of a strictly convex gradient, found
  * by semismooth Newton with Jacobi-preconditioned conjugate-gradient inner
- * solves (FP64, one workgroup per sample, n <= 256).  Models with beta2 > 0 and a sample with
+ * solves (one workgroup per sample, n <= 256; the Newton residual and its
+ * convergence test are FP64, the on-chip variant for n = 64, 88, 128 keeps
+ * the CG direction in FP32 and the CG solution as an FP32 pair).  Models with beta2 > 0 and a sample with
  * xi_h <= 0 (a non-convex step with possibly several solutions) are
  * NLCH_EUNSUPPORTED.  A sample whose Newton iteration does not converge
  * within its iteration cap gets a NaN state and output of interest.
@@ -71,6 +73,14 @@
  *    FP32, every stored value rounded to nearest-even).
  *  - hip_stream is a hipStream_t (NULL = the null stream).
  *  - Calls that enqueue work on the same device buffers must not overlap.
+ *  - Calls with the same signature (models, samples, precision, algorithm
+ *    word, and whether it is nlch_step or a batch solve) share small device
+ *    scratch the library keeps for that signature (output-of-interest chunk
+ *    sums, energy partials, beta2 > 0 workspaces).  The library orders such
+ *    calls: a call on another stream than the previous one of its signature
+ *    waits for it with an event.  Work enqueued while hip_stream is capturing
+ *    a graph is not ordered this way: the caller orders captured calls of
+ *    one signature.
  */
 #ifndef NLCH_H
 #define NLCH_H

@@ -14,11 +14,17 @@
 // Newton on F: the Jacobian tau A + diag(1/xi where |z| < xi) is symmetric
 // positive definite and each system is solved by conjugate gradients with
 // the matrix-free 5-point stencil; the step length comes from Armijo
-// backtracking on Phi.  Newton starts from z = xi u_old, so a step depends on
-// u_old only.
+// backtracking on Phi.  The first step of a solve starts Newton from
+// z = xi u_old; every later step of the same solve starts from the previous
+// step's z, kept in the workspace (warm start), so a solve split over several
+// calls agrees with one call to the Newton tolerance, not bit for bit.
 //
-// One workgroup per sample, FP64 throughout, vectors in a per-sample global
-// workspace.  Every decision is taken on block-reduced scalars, so control
+// One workgroup per sample.  k_b2_step keeps every vector in FP64 in a
+// per-sample global workspace.  The on-chip variant k_b2_step_lds keeps the
+// Newton-level vectors (z, r, F, the Newton direction) and the CG residual in
+// FP64, but the CG direction in FP32 and the CG solution as an FP32 pair (high
+// part in LDS, low part in registers); the Newton residual test is FP64 in
+// both.  Every decision is taken on block-reduced scalars, so control
 // flow is uniform across the workgroup; every loop has a fixed cap, and a
 // sample whose Newton iteration has not converged at the cap gets a NaN
 // state (hence a NaN output of interest).

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "nlch.h"
+#include "nlch_host.h"
 #include "nlch_internal.h"
 
 namespace nlch {
@@ -87,7 +88,7 @@ using namespace nlch;
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char *fmt, ...) {
+int nlch::fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -99,13 +100,6 @@ static int fail(int code, const char *fmt, ...) {
 
 int nlch::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 
-#define HIP_TRY(expr)                                                             \
-    do {                                                                          \
-        hipError_t e_ = (expr);                                                   \
-        if (e_ != hipSuccess)                                                     \
-            return fail(NLCH_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
-    } while (0)
-
 // ---------------------------------------------------------------- geometry --
 
 static int64_t isqrt64(int64_t v) {
@@ -116,22 +110,11 @@ static int64_t isqrt64(int64_t v) {
     return r;
 }
 
-struct ModelInfo {
-    int64_t R2 = 0, N = 0;
-    int m = 0;
-    int lo = 0;                  // ring width: m under a volume constraint, else 0
-    int side = 0;                // side of a stored state, n + 2 lo
-    std::vector<int32_t> halfw;  // |dy| = 0..m
-    double sum_e = 0.0;          // sum_{d in D} e_d, e_d exact 2-D unit weights
-    double ce_sep = 0.0;         // sum_{d in D} g(|dy|) g(|dx|)
-    std::vector<double> g;       // g(k), k = 0..m
-    std::vector<double> e2;      // e(|dy|, |dx|), (m+1) x (m+1)
-};
 
-static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool nlch::finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Validates a model and builds its tables (host only, no device work).
-static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) {
+int nlch::analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) {
     if (md.n < 3 || md.n > 32768)
         return fail(NLCH_EINVAL, "%s: n = %d outside [3, 32768]", what, md.n);
     if (md.kernel != NLCH_KERNEL_CONSTANT && md.kernel != NLCH_KERNEL_GAUSSIAN)
@@ -199,12 +182,9 @@ static int analyze_model(const nlch_model &md, ModelInfo &mi, const char *what) 
     return NLCH_OK;
 }
 
-struct Coef {
-    double c_gamma_h, xi_h, c1, a, b;
-};
 
-static int sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, double amp,
-                       Coef &c, const char *what) {
+int nlch::sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, double amp,
+                      Coef &c, const char *what) {
     const double h2 = 1.0 / ((double)md.n * md.n);
     c.c_gamma_h = h2 * amp * mi.sum_e;
     c.xi_h = c.c_gamma_h - c_F;
@@ -220,6 +200,114 @@ static int sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, do
     c.b = c.c1 * h2 * amp;
     return NLCH_OK;
 }
+
+size_t nlch::prec_size(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }
+
+static float rne_f32(double v) { return (float)v; }
+
+// Chooses the kernel variant for a model under the requested algorithm.
+int nlch::choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nlch_model &md,
+                   bool batch, int *variant) {
+    if (md.beta2 > 0.0) {
+        // the coupled step has one kernel, whatever the algorithm word asks
+        if (base == NLCH_ALGO_RESIDENT)
+            return fail(NLCH_EUNSUPPORTED, "RESIDENT is built for beta2 = 0 only");
+        *variant = kB2;
+        return NLCH_OK;
+    }
+    const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n,
+                                                 mi.lo != 0);
+    const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
+    switch (base) {
+        case NLCH_ALGO_AUTO:
+            *variant = res ? kResident : (row ? kRowrun : kDirect);
+            return NLCH_OK;
+        case NLCH_ALGO_DIRECT:
+            *variant = kDirect;
+            return NLCH_OK;
+        case NLCH_ALGO_ROWRUN:
+            if (!row)
+                return fail(NLCH_EUNSUPPORTED, "ROWRUN is not built for R2 = %lld",
+                            (long long)mi.R2);
+            *variant = kRowrun;
+            return NLCH_OK;
+        case NLCH_ALGO_RESIDENT:
+            if (!batch) return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
+            if (!res)
+                return fail(NLCH_EUNSUPPORTED,
+                            "RESIDENT needs n = 64 or 128, a sample that fits in LDS and a "
+                            "built R2 (n = %d, R2 = %lld)", md.n, (long long)mi.R2);
+            *variant = kResident;
+            return NLCH_OK;
+        default:
+            return fail(NLCH_EINVAL, "unknown algorithm %d", base);
+    }
+}
+
+
+void nlch::fill_model_geo(const nlch_model &md, const ModelInfo &mi, int64_t e_off,
+                          ModelGeo &gm) {
+    std::memset(&gm, 0, sizeof(gm));
+    gm.n = mi.side;
+    gm.lo = mi.lo;
+    gm.m = mi.m;
+    gm.R2 = (int32_t)mi.R2;
+    gm.N = (int32_t)mi.N;
+    gm.kernel = md.kernel;
+    gm.e_off = e_off;
+    gm.ced = mi.ce_sep;
+    gm.cef = rne_f32(mi.ce_sep);
+    gm.tau_b1 = md.tau * md.beta1;
+    gm.tau_b2 = md.tau * md.beta2;
+    for (int k = 0; k <= mi.m; ++k) {
+        gm.gd[k] = mi.g[k];
+        gm.gf[k] = rne_f32(mi.g[k]);
+        gm.halfw[k] = mi.halfw[k];
+    }
+}
+
+void nlch::fill_sample_desc(const nlch_model &md, const ModelInfo &mi, const nlch_sample &sm,
+                            const Coef &c, SampleDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    d.offset = sm.offset;
+    d.model = sm.model;
+    d.n = mi.side;
+    d.a = c.a;
+    d.b = c.b;
+    d.af = rne_f32(c.a);
+    d.bf = rne_f32(c.b);
+    const double h2 = 1.0 / ((double)md.n * md.n);
+    d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
+    d.e_pot = 0.5 * h2 * sm.c_F;
+    d.xi = c.xi_h;
+}
+
+Group nlch::make_group(const nlch_model &md, const ModelInfo &mi, int model_index, int n_ids,
+                       int prec) {
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.nids = n_ids;
+    g.n = mi.side;
+    g.lo = mi.lo;
+    g.ni = md.n;
+    g.m = mi.m;
+    g.R2 = (int32_t)mi.R2;
+    g.kernel = md.kernel;
+    g.model = model_index;
+    g.ta_bytes = prec == kF64 ? 8 : 4;
+    return g;
+}
+
+int nlch::check_algo_flags(int32_t algo) {
+    const int32_t known = 0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_NOGRAPH | NLCH_ALGO_CHECK_FINITE |
+                          NLCH_ALGO_AUTOTUNE;
+    if (algo & ~known) return fail(NLCH_EINVAL, "unknown algorithm flags 0x%x", algo & ~known);
+    const int base = algo & 0xff;
+    if (base < NLCH_ALGO_AUTO || base > NLCH_ALGO_RESIDENT)
+        return fail(NLCH_EINVAL, "unknown algorithm %d", base);
+    return NLCH_OK;
+}
+
 
 // ------------------------------------------------------------ device state --
 
@@ -244,8 +332,16 @@ struct Batch {
     std::vector<int> variant;            // per group
     bool tuned = false;
     std::map<std::vector<uint8_t>, hipGraphExec_t> graphs;
+    // Calls with the same signature share the tables and device scratch
+    // above (OoI chunk sums, energy partials, beta2 workspaces): `done` is
+    // recorded after each call's work on its stream `last`, and a call on
+    // another stream waits for it first.
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
     ~Batch() {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (done) (void)hipEventDestroy(done);
     }
 };
 
@@ -297,49 +393,6 @@ void append_bytes(std::vector<uint8_t> &k, const T &v) {
     k.insert(k.end(), p, p + sizeof(T));
 }
 
-size_t prec_size(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }
-
-float rne_f32(double v) { return (float)v; }
-
-// Chooses the kernel variant for a model under the requested algorithm.
-int choose_variant(int base, int prec, bool acc64, const ModelInfo &mi, const nlch_model &md,
-                   bool batch, int *variant) {
-    if (md.beta2 > 0.0) {
-        // the coupled step has one kernel, whatever the algorithm word asks
-        if (base == NLCH_ALGO_RESIDENT)
-            return fail(NLCH_EUNSUPPORTED, "RESIDENT is built for beta2 = 0 only");
-        *variant = kB2;
-        return NLCH_OK;
-    }
-    const bool res = batch && resident_supported(prec, acc64, (int)mi.R2, md.kernel, md.n,
-                                                 mi.lo != 0);
-    const bool row = rowrun_supported(prec, acc64, (int)mi.R2, md.kernel);
-    switch (base) {
-        case NLCH_ALGO_AUTO:
-            *variant = res ? kResident : (row ? kRowrun : kDirect);
-            return NLCH_OK;
-        case NLCH_ALGO_DIRECT:
-            *variant = kDirect;
-            return NLCH_OK;
-        case NLCH_ALGO_ROWRUN:
-            if (!row)
-                return fail(NLCH_EUNSUPPORTED, "ROWRUN is not built for R2 = %lld",
-                            (long long)mi.R2);
-            *variant = kRowrun;
-            return NLCH_OK;
-        case NLCH_ALGO_RESIDENT:
-            if (!batch) return fail(NLCH_EINVAL, "RESIDENT applies to nlch_solve_batch only");
-            if (!res)
-                return fail(NLCH_EUNSUPPORTED,
-                            "RESIDENT needs n = 64 or 128, a sample that fits in LDS and a "
-                            "built R2 (n = %d, R2 = %lld)", md.n, (long long)mi.R2);
-            *variant = kResident;
-            return NLCH_OK;
-        default:
-            return fail(NLCH_EINVAL, "unknown algorithm %d", base);
-    }
-}
-
 // Builds (or finds) the device tables for a batch.
 int get_batch(const nlch_model *models, int32_t n_models, const std::vector<ModelInfo> &mi,
               const nlch_sample *samples, int64_t n_samples, int prec, int algo, bool is_batch,
@@ -350,6 +403,9 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     append_bytes(key, dev);
     append_bytes(key, prec);
     append_bytes(key, algo & (0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_AUTOTUNE));
+    // nlch_step and nlch_solve_batch choose kernels differently (RESIDENT is
+    // a whole-solve kernel): the same model and sample must not share a batch
+    append_bytes(key, is_batch);
     append_bytes(key, n_models);
     append_bytes(key, n_samples);
     for (int i = 0; i < n_models; ++i) append_bytes(key, models[i]);
@@ -369,30 +425,14 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
     std::unique_ptr<Batch> b(new Batch());
     b->key = key;
     b->device = dev;
+    HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
 
     // Geometry and weight tables.
     std::vector<ModelGeo> geo(n_models);
     std::vector<float> ewf;
     std::vector<double> ewd;
     for (int i = 0; i < n_models; ++i) {
-        ModelGeo &gm = geo[i];
-        std::memset(&gm, 0, sizeof(gm));
-        gm.n = mi[i].side;
-        gm.lo = mi[i].lo;
-        gm.m = mi[i].m;
-        gm.R2 = (int32_t)mi[i].R2;
-        gm.N = (int32_t)mi[i].N;
-        gm.kernel = models[i].kernel;
-        gm.e_off = (int64_t)ewd.size();
-        gm.ced = mi[i].ce_sep;
-        gm.cef = rne_f32(mi[i].ce_sep);
-        gm.tau_b1 = models[i].tau * models[i].beta1;
-        gm.tau_b2 = models[i].tau * models[i].beta2;
-        for (int k = 0; k <= mi[i].m; ++k) {
-            gm.gd[k] = mi[i].g[k];
-            gm.gf[k] = rne_f32(mi[i].g[k]);
-            gm.halfw[k] = mi[i].halfw[k];
-        }
+        fill_model_geo(models[i], mi[i], (int64_t)ewd.size(), geo[i]);
         for (double e : mi[i].e2) {
             ewd.push_back(e);
             ewf.push_back(rne_f32(e));
@@ -407,19 +447,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         snprintf(what, sizeof(what), "sample %lld", (long long)s);
         int rc = sample_coef(models[sm.model], mi[sm.model], sm.c_F, sm.kernel_amp, c, what);
         if (rc) return rc;
-        SampleDesc &d = sd[(size_t)s];
-        std::memset(&d, 0, sizeof(d));
-        d.offset = sm.offset;
-        d.model = sm.model;
-        d.n = mi[sm.model].side;
-        d.a = c.a;
-        d.b = c.b;
-        d.af = rne_f32(c.a);
-        d.bf = rne_f32(c.b);
-        const double h2 = 1.0 / ((double)models[sm.model].n * models[sm.model].n);
-        d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
-        d.e_pot = 0.5 * h2 * sm.c_F;
-        d.xi = c.xi_h;
+        fill_sample_desc(models[sm.model], mi[sm.model], sm, c, sd[(size_t)s]);
     }
     // Groups: per model, samples in batch order.
     std::vector<std::vector<int32_t>> per_model(n_models);
@@ -432,17 +460,7 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         int variant = 0;
         int rc = choose_variant(base, prec, acc64, mi[i], models[i], is_batch, &variant);
         if (rc) return rc;
-        Group g;
-        std::memset(&g, 0, sizeof(g));
-        g.nids = (int32_t)per_model[i].size();
-        g.n = mi[i].side;
-        g.lo = mi[i].lo;
-        g.ni = models[i].n;
-        g.m = mi[i].m;
-        g.R2 = (int32_t)mi[i].R2;
-        g.kernel = models[i].kernel;
-        g.model = i;
-        g.ta_bytes = prec == kF64 ? 8 : 4;
+        Group g = make_group(models[i], mi[i], i, (int)per_model[i].size(), prec);
         id_off.push_back(ids.size());
         ids.insert(ids.end(), per_model[i].begin(), per_model[i].end());
         b->groups.push_back(g);
@@ -477,9 +495,39 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         g.sd = reinterpret_cast<const SampleDesc *>(b->sd.p);
         g.ids = reinterpret_cast<const int32_t *>(b->ids.p) + id_off[gi];
     }
-    if (g_batches.size() >= kMaxBatches) g_batches.erase(g_batches.begin());
+    if (g_batches.size() >= kMaxBatches) {
+        // work enqueued earlier may still read the oldest batch's tables
+        HIP_TRY(hipDeviceSynchronize());
+        g_batches.erase(g_batches.begin());
+    }
     g_batches.push_back(std::move(b));
     *out = g_batches.back().get();
+    return NLCH_OK;
+}
+
+// True when s is capturing a graph (the caller then orders the captured
+// work; events recorded outside the capture cannot be waited on inside it).
+int stream_capturing(hipStream_t s, bool *cap) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &st));
+    *cap = st != hipStreamCaptureStatusNone;
+    return NLCH_OK;
+}
+
+// Orders a call's work after the previous call of the same batch when the
+// two run on different streams (they share the batch's device scratch).
+int batch_begin(Batch &b, hipStream_t s, bool *cap) {
+    int rc = stream_capturing(s, cap);
+    if (rc) return rc;
+    if (!*cap && b.used && b.last != s) HIP_TRY(hipStreamWaitEvent(s, b.done, 0));
+    return NLCH_OK;
+}
+
+int batch_end(Batch &b, hipStream_t s, bool cap) {
+    if (cap) return NLCH_OK;
+    HIP_TRY(hipEventRecord(b.done, s));
+    b.last = s;
+    b.used = true;
     return NLCH_OK;
 }
 
@@ -698,16 +746,6 @@ int enqueue_solve(Batch &b, DevCtx &ctx, int prec, bool acc64, int nsteps, void 
     return NLCH_OK;
 }
 
-int check_algo_flags(int32_t algo) {
-    const int32_t known = 0xff | NLCH_ALGO_ACC64 | NLCH_ALGO_NOGRAPH | NLCH_ALGO_CHECK_FINITE |
-                          NLCH_ALGO_AUTOTUNE;
-    if (algo & ~known) return fail(NLCH_EINVAL, "unknown algorithm flags 0x%x", algo & ~known);
-    const int base = algo & 0xff;
-    if (base < NLCH_ALGO_AUTO || base > NLCH_ALGO_RESIDENT)
-        return fail(NLCH_EINVAL, "unknown algorithm %d", base);
-    return NLCH_OK;
-}
-
 }  // namespace
 
 // nlch_solve_batch and nlch_solve_batch_energy (energy_out nullable here).
@@ -780,7 +818,14 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     Batch *b = nullptr;
     rc = get_batch(models, n_models, mi, samples, n_samples, precision, algo, true, &b);
     if (rc) return rc;
+    // the cached batch's kernels decide whether scratch is read
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        if (b->variant[gi] != kResident && !scratch)
+            return fail(NLCH_EINVAL, "scratch must be non-NULL unless every sample runs RESIDENT");
     hipStream_t s = (hipStream_t)hip_stream;
+    bool capturing = false;
+    rc = batch_begin(*b, s, &capturing);
+    if (rc) return rc;
 
     if (algo & NLCH_ALGO_CHECK_FINITE) {
         HIP_TRY(hipMemsetAsync(ctx->counter, 0, sizeof(unsigned int), s));
@@ -820,9 +865,12 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     rc = ensure_b2ws(*b);
     if (rc) return rc;
 
-    if (algo & NLCH_ALGO_NOGRAPH)
-        return enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
-                             energy_out, n_samples, s);
+    if (algo & NLCH_ALGO_NOGRAPH) {
+        rc = enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
+                           energy_out, n_samples, s);
+        if (rc) return rc;
+        return batch_end(*b, s, capturing);
+    }
 
     std::vector<uint8_t> gk;
     append_bytes(gk, state);
@@ -864,7 +912,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         it = b->graphs.emplace(gk, exec).first;
     }
     HIP_TRY(hipGraphLaunch(it->second, s));
-    return NLCH_OK;
+    return batch_end(*b, s, capturing);
 }
 
 // --------------------------------------------------------------------- ABI --
@@ -964,12 +1012,15 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     hipStream_t s = (hipStream_t)hip_stream;
     rc = ensure_b2ws(*b);
     if (rc) return rc;
+    bool capturing = false;
+    rc = batch_begin(*b, s, &capturing);
+    if (rc) return rc;
     const Group &g = b->groups[0];
     // the step writes the updated block only; the fixed ring is carried over
     if (g.lo != 0) HIP_TRY(launch_project(precision, g, u_in, u_out, s));
     HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
     if (ooi_out) HIP_TRY(launch_ooi(precision, g, u_out, ooi_out, 2, s));
-    return NLCH_OK;
+    return batch_end(*b, s, capturing);
 }
 
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
