@@ -396,3 +396,27 @@ def test_step_sites_rejects_out_of_range_sites(orc):
         with pytest.raises(Exception):
             orc.step_sites(u, np.array(bad, dtype=np.int64), n, 2 / n, 0, 1.0, 0.0,
                            1.0, 1.0, 0.01)
+
+
+def test_trajectory_goldens_are_consistent():
+    """The stored full-size oracle results parse, name the recipes' shapes,
+    satisfy f_1 = (1 + mean)/2 (eq. ooi) and keep every stored value in
+    [-1, 1]; the sites include the four corners."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_trajectory_goldens", os.path.join(GOLDEN, "make_trajectory_goldens.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    g = mod.read_goldens(os.path.join(GOLDEN, "trajectories.txt"))
+    assert set(g) == set(mod.CASES)
+    for name, v in g.items():
+        recipe, idx, prec, nsteps = mod.CASES[name]
+        assert (v["recipe"], v["sample"], v["precision"], v["nsteps"]) == (recipe, idx, prec,
+                                                                            nsteps)
+        w = synth.workload(recipe)
+        assert v["n"] == w.models[w.samples[idx].model].n
+        assert abs(v["f1"] - 0.5 * (1 + v["mean"])) <= 1e-16
+        assert np.all(np.abs(v["values"]) <= 1.0)
+        n = v["n"]
+        assert {0, n - 1, (n - 1) * n, n * n - 1} <= set(v["sites"].tolist())
+        assert np.array_equal(v["sites"], mod.case_sites(n, 1000 + idx))
