@@ -134,6 +134,8 @@ def main():
                     help="the CPU oracle baseline adds chunks of 16 samples until "
                          "this much oracle time is spent")
     ap.add_argument("--fp64-samples", type=int, default=4)
+    ap.add_argument("--resident-cols", type=int, default=0,
+                    help="layout of the LDS-resident kernel: columns per lane (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     args = ap.parse_args()
@@ -176,6 +178,7 @@ def main():
 
     stream = torch.cuda.Stream(device=dev)
     precision = nlch.PRECISIONS[prec]
+    nlch.nlch_set_resident_shape(args.resident_cols)
     level_counts = w.level_counts or [S]
     # MFMC moments: levels are contiguous in sample order, HF first.
     level_ptrs, off = [], 0

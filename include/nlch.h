@@ -263,6 +263,15 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
  * Host only; returns NLCH_EINVAL for values outside those ranges. */
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
 
+/* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
+ * calls in this process: cols_per_lane = 4 (lanes own 4 adjacent columns, a
+ * wave walks two 16-row bands, windows read with 16-byte LDS loads; built for
+ * FP32 state on 128^2 lattices of the periodic domain without the energy
+ * trace), 2 (lanes own 2 columns, one band per wave; every resident case), or
+ * 0 (the default: 4 where built, else 2).  Both layouts give bit-identical
+ * results.  Host only; NLCH_EINVAL for other values. */
+int nlch_set_resident_shape(int32_t cols_per_lane);
+
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
  * y_dev[j]: device pointer to the outputs of model j+1, the output for
  * parameter draw i at y_dev[j][i * y_stride] for i < m[j] (draws shared

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(
                 const TA diff = uc - row[dx];
                 if (GAUSS) {
                     const int adx = dx < 0 ? -dx : dx;
-                    acc += ewm[ady * (m + 1) + adx] * diff;
+                    acc = madd(ewm[ady * (m + 1) + adx], diff, acc);
                 } else {
                     acc += diff;
                 }

@@ -549,6 +549,7 @@ struct TuneVal {
 };
 std::map<TuneKey, TuneVal> g_tuned;
 TuneVal g_force{0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods)
+int g_force_res_cols = 0;     // nlch_set_resident_shape
 
 void set_shape(Group &g, const TuneVal &v) {
     g.tune_R = v.R;
@@ -858,6 +859,9 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         for (Group &g : b->groups) set_shape(g, {0, 0, 0, 0});
     }
 
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        b->groups[gi].res_cols = b->variant[gi] == kResident ? g_force_res_cols : 0;
+
     if (energy_out) {
         rc = ensure_epart(*b);
         if (rc) return rc;
@@ -883,6 +887,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         append_bytes(gk, g.tune_B);
         append_bytes(gk, g.tune_W);
         append_bytes(gk, g.tune_L);
+        append_bytes(gk, g.res_cols);
     }
     auto it = b->graphs.find(gk);
     if (it == b->graphs.end()) {
@@ -1030,6 +1035,14 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
                                  "periods 0..64, B >= 0)");
     std::lock_guard<std::mutex> lk(g_mu);
     g_force = {R, B, W, periods};
+    return NLCH_OK;
+}
+
+int nlch_set_resident_shape(int32_t cols_per_lane) {
+    if (!(cols_per_lane == 0 || cols_per_lane == 2 || cols_per_lane == 4))
+        return fail(NLCH_EINVAL, "columns per lane must be 0 (default), 2 or 4");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_res_cols = cols_per_lane;
     return NLCH_OK;
 }
 

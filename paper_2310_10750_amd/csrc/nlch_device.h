@@ -61,10 +61,24 @@ __device__ __forceinline__ float geo_ce<float>(const ModelGeo *g) { return g->ce
 template <>
 __device__ __forceinline__ double geo_ce<double>(const ModelGeo *g) { return g->ced; }
 
-// v = u + (a u - b Lsum), projected.
+// Fused multiply-add a b + c (one rounding).  The stencil units are
+// compiled without automatic contraction, so every fused operation of the
+// path is written out here and every kernel rounds the same operations the
+// same way (results do not depend on how a kernel's code was scheduled).
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Lsum = ce u - G (unit-amplitude operator sum from the disc sum G).
+template <class TA>
+__device__ __forceinline__ TA lsum_of(TA ce, TA u, TA G) {
+    return madd(ce, u, -G);
+}
+
+// v = u + (a u - b Lsum), projected.  Sign-symmetric: update(-u, -Lsum) is
+// -update(u, Lsum) exactly.
 template <class TA>
 __device__ __forceinline__ TA update(TA u, TA lsum, TA a, TA b) {
-    TA t = a * u - b * lsum;
+    const TA t = madd(-b, lsum, a * u);
     return clamp1(u + t);
 }
 

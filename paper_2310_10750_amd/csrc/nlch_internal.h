@@ -68,6 +68,7 @@ struct Group {
     int32_t tune_R, tune_B;  // streaming shape (0 = heuristic): columns per
     int32_t tune_W, tune_L;  //   lane, band rows, waves per band, rows per wave
     int32_t ta_bytes;        // size of the arithmetic type (4 or 8)
+    int32_t res_cols;        // resident kernel: columns per lane (0 = default)
 };
 
 // Heuristic streaming shape of the row-run kernel: lanes own R columns of a
