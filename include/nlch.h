@@ -204,6 +204,23 @@ int nlch_model_constants(const nlch_model *model, double *c_gamma_h,
 int nlch_step(const nlch_model *model, int32_t precision, int32_t algo,
               const void *u_in, void *u_out, double *ooi_out, void *hip_stream);
 
+/* nlch_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as nlch_step, but the model's device
+ * tables and the chunk sums of the output-of-interest reduction live in one
+ * static device area of 128 KiB per GPU, written by small kernels whose
+ * arguments carry the values: the call allocates no device memory and copies
+ * nothing from the host.  Limits: beta2 = 0 only, and the tables plus
+ * ceil(n^2 / 16384) doubles of chunk sums (when ooi_out != NULL) must fit
+ * the area: n <= 16287 on the row-run kernel, down to n <= 14354 on the
+ * direct kernel at the widest horizon (m = 48); larger requests are
+ * NLCH_EUNSUPPORTED before any device work.  Every call on a GPU uses that
+ * GPU's area and leaves its tables there: calls that overlap on one GPU
+ * (other streams, concurrent graph replays) race on it, so the caller must
+ * order them. */
+int nlch_step_noalloc(const nlch_model *model, int32_t precision, int32_t algo,
+                      const void *u_in, void *u_out, double *ooi_out, void *hip_stream);
+
 /* Solve a batch: for every sample s, u^0 = clamp(state_s, -1, 1) (the initial
  * datum projected onto [-1, 1]), nsteps steps of the scheme with the sample's
  * model, c_F and amplitude, then u^nsteps is left in state_s and

@@ -103,6 +103,8 @@ def load():
     lib.nlch_model_constants.restype = ctypes.c_int
     lib.nlch_step.argtypes = [ctypes.POINTER(nlch_model), i32, i32, vp, vp, vp, vp]
     lib.nlch_step.restype = ctypes.c_int
+    lib.nlch_step_noalloc.argtypes = [ctypes.POINTER(nlch_model), i32, i32, vp, vp, vp, vp]
+    lib.nlch_step_noalloc.restype = ctypes.c_int
     lib.nlch_solve_batch.argtypes = [ctypes.POINTER(nlch_model), i32,
                                      ctypes.POINTER(nlch_sample), i64, i32, i32,
                                      i32, vp, vp, vp, vp]
@@ -204,6 +206,14 @@ def nlch_step(model: nlch_model, precision: int, algo: int, u_in, u_out,
               ooi_out=None, stream=None) -> None:
     _check(load().nlch_step(ctypes.byref(model), precision, algo, _ptr(u_in),
                             _ptr(u_out), _ptr(ooi_out), _stream(stream)))
+
+
+def nlch_step_noalloc(model: nlch_model, precision: int, algo: int, u_in, u_out,
+                      ooi_out=None, stream=None) -> None:
+    """nlch_step with every device table and partial sum in the library's
+    static device area (no device allocation)."""
+    _check(load().nlch_step_noalloc(ctypes.byref(model), precision, algo, _ptr(u_in),
+                                    _ptr(u_out), _ptr(ooi_out), _stream(stream)))
 
 
 def nlch_solve_batch(models, samples, nsteps: int, precision: int, algo: int, state,
