@@ -39,7 +39,14 @@ METRIC = ("site-steps/s & HBM/LDS GB/s: batched FP32 vs 1-sample FP64, "
 # multiply-add each): 256 CUs x 128 FP32 lanes per clock x 2.4 GHz = 78.6 T/s,
 # the published 157.3 TFLOP/s with a fused multiply-add counted as one.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+# Rates the peak-measurement program (paper_2310_10750_amd/peaks) reaches on
+# MI355X with this build's flags: FP32 adds, and LDS reads of 8 and 16 bytes
+# per lane (lane-contiguous).  No LDS bandwidth of CDNA4 is published beside
+# the 160 KB capacity; the measured rates are the LDS ceiling used here.
+MEASURED_ADD_TOPS = 71.9
+MEASURED_LDS_GBS = {"8B": 72800.0, "16B": 95300.0}
 
 
 def log(*a):
@@ -51,6 +58,10 @@ def log(*a):
 KERNEL_SOURCES = {
     "k_resident": ["kern_rowrun_impl.h", "kern_rowrun_dispatch.h", "kern_rowrun_f32.hip",
                    "nlch_device.h", "nlch_internal.h"],
+    "k_resident4": ["kern_rowrun_impl.h", "kern_resident4.hip", "nlch_device.h",
+                    "nlch_internal.h"],
+    "k_resident4h": ["kern_rowrun_impl.h", "kern_resident4.hip", "nlch_device.h",
+                     "nlch_internal.h"],
 }
 
 
@@ -70,9 +81,20 @@ def algorithmic_ops(m: int, kernel: int) -> int:
     """VALU lane-operations per site-step of the row-run evaluation: 2m for the
     window sums (m pair adds, m accumulations -- fused multiply-adds for the
     Gaussian kernel), 2m+1 for adding the window sums of the 2m+1 disc rows
-    (adds, or fused multiply-adds), and 6 for the update and the projection.
-    A fused multiply-add counts as one lane-operation."""
-    return 2 * m + (2 * m + 1) + 6
+    (adds, or fused multiply-adds), and 5 for the update from the disc sum
+    (a multiply, a fused multiply-add, an add) and the projection (a maximum
+    and a minimum).  A fused multiply-add counts as one lane-operation."""
+    return 2 * m + (2 * m + 1) + 5
+
+
+def algorithmic_flops(m: int, kernel: int) -> int:
+    """The same work in floating-point operations, a fused multiply-add
+    counted as two and the projection's maximum and minimum as none: constant
+    kernel 2m + (2m+1) + 4; Gaussian kernel (m of the window terms and all
+    2m+1 row sums are fused multiply-adds) 3m + 2(2m+1) + 4."""
+    if kernel == 1:
+        return 3 * m + 2 * (2 * m + 1) + 4
+    return 2 * m + (2 * m + 1) + 4
 
 
 def stored_counters(kernel_name: str, workload: str):
@@ -134,8 +156,9 @@ def main():
                     help="the CPU oracle baseline adds chunks of 16 samples until "
                          "this much oracle time is spent")
     ap.add_argument("--fp64-samples", type=int, default=4)
-    ap.add_argument("--resident-cols", type=int, default=0,
-                    help="layout of the LDS-resident kernel: columns per lane (0 = default)")
+    ap.add_argument("--resident-shape", default="0,0",
+                    help="layout of the LDS-resident kernel: columns,rows per lane "
+                         "(0,0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     args = ap.parse_args()
@@ -178,7 +201,7 @@ def main():
 
     stream = torch.cuda.Stream(device=dev)
     precision = nlch.PRECISIONS[prec]
-    nlch.nlch_set_resident_shape(args.resident_cols)
+    nlch.nlch_set_resident_shape(*[int(v) for v in args.resident_shape.split(",")])
     level_counts = w.level_counts or [S]
     # MFMC moments: levels are contiguous in sample order, HF first.
     level_ptrs, off = [], 0
@@ -226,15 +249,26 @@ def main():
     resident = all(mm.n in (64, 128) and mm.beta2 == 0 for mm in w.models) and \
         (args.algo & 0xff) in (0, 3)
     kname = "k_resident" if resident else "k_rowrun"
-    ops = sum(algorithmic_ops(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
-                              w.models[s.model].kernel) * w.models[s.model].n ** 2
-              for s in w.samples) * w.nsteps
+    shape = tuple(int(v) for v in args.resident_shape.split(","))
+    if resident and prec == "f32" and all(mm.n == 128 and not mm.boundary for mm in w.models) \
+            and mdisc <= 8 and shape != (2, 16):
+        kname = "k_resident4" if shape == (4, 16) else "k_resident4h"
+    def per_site(fn):
+        return sum(fn(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
+                      w.models[s.model].kernel) * w.models[s.model].n ** 2
+                   for s in w.samples) * w.nsteps
+    ops, flops = per_site(algorithmic_ops), per_site(algorithmic_flops)
     achieved = ops / (solve_ms * 1e-3) / 1e12
+    tflops = flops / (solve_ms * 1e-3) / 1e12
     traffic = stored_traffic(kname, w.name)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "unit": "T lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic, "kernel": kname,
-                "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel)}
+                "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel),
+                "flops_per_site_step": algorithmic_flops(mdisc, m0.kernel),
+                "achieved_tflops": round(tflops, 3), "peak_tflops": FP32_PEAK_TFLOPS,
+                "frac_flops": round(tflops / FP32_PEAK_TFLOPS, 4),
+                "frac_measured_add_rate": round(achieved / MEASURED_ADD_TOPS, 4)}
     if any(mm.beta2 > 0 for mm in w.models):
         # an iterative solve per step (Newton with conjugate-gradient inner
         # solves): no fixed algorithmic count per site-step to price
@@ -247,8 +281,17 @@ def main():
     lds = None
     if ctr and ctr.get("lds_bytes_per_launch") and roofline is not None:
         lb = ctr["lds_bytes_per_launch"]
+        gbs = lb / (solve_ms * 1e-3) / 1e9
+        width = ctr.get("lds_read_width", "8B")
         lds = {"bytes_per_launch": lb, "bytes_per_site_step": round(lb / site_steps, 2),
-               "achieved_gbs": round(lb / (solve_ms * 1e-3) / 1e9, 1)}
+               "achieved_gbs": round(gbs, 1), "read_width": width,
+               "frac_measured_8B": round(gbs / MEASURED_LDS_GBS["8B"], 4),
+               "frac_measured_16B": round(gbs / MEASURED_LDS_GBS["16B"], 4)}
+        # the pipe nearer its ceiling: VALU against the measured add rate, LDS
+        # against the measured rate of the kernel's read width
+        f_lds = gbs / MEASURED_LDS_GBS[width]
+        roofline["binding_pipe"] = "lds" if f_lds > roofline["frac_measured_add_rate"] else "valu"
+        roofline["frac_lds"] = round(f_lds, 4)
 
     out = {
         "metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1,

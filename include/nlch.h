@@ -281,13 +281,21 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
 
 /* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
- * calls in this process: cols_per_lane = 4 (lanes own 4 adjacent columns, a
- * wave walks two 16-row bands, windows read with 16-byte LDS loads; built for
- * FP32 state on 128^2 lattices of the periodic domain without the energy
- * trace), 2 (lanes own 2 columns, one band per wave; every resident case), or
- * 0 (the default: 4 where built, else 2).  Both layouts give bit-identical
- * results.  Host only; NLCH_EINVAL for other values. */
-int nlch_set_resident_shape(int32_t cols_per_lane);
+ * calls in this process: each lane owns cols_per_lane adjacent columns and
+ * walks rows_per_lane rows of a 16-row band.
+ *   (2, 16): one band per wave; every resident case.
+ *   (4, 16): two bands per wave (one per half-wave), 16-byte LDS window
+ *            loads; bit-identical to (2, 16).
+ *   (4, 8):  one band per wave, its two half-waves walking 8 rows each and
+ *            adding each other's sums with a lane swap; 8 waves per sample,
+ *            so that a CU's two resident samples give four waves per SIMD.
+ *            Band sums are formed in two parts, so results differ from
+ *            (2, 16) by FP32 rounding only.
+ *   (0, 0):  the default, (4, 8) where built, else (2, 16).
+ * The four-column layouts are built for FP32 state on 128^2 lattices of the
+ * periodic domain without the energy trace.  Host only; NLCH_EINVAL for other
+ * values. */
+int nlch_set_resident_shape(int32_t cols_per_lane, int32_t rows_per_lane);
 
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
  * y_dev[j]: device pointer to the outputs of model j+1, the output for

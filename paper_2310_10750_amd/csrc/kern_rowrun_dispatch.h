@@ -101,25 +101,16 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
     if (vol)
         return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, true>)
                           : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, true>);
+    if constexpr (std::is_same<TS, float>::value && std::is_same<TA, float>::value) {
+        // four columns per lane where built, unless two are asked for (with
+        // or without the energy trace, so that the trace runs the layout of
+        // the plain solve)
+        if (g.ni == 128 && g.res_cols != 2 && resident4_built(g.R2))
+            return resident4_launch_f32(g, state, nsteps, ooi, s, energy, estride);
+    }
     if (energy)
         return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>)
                           : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, true, false>);
-    if constexpr (std::is_same<TS, float>::value && std::is_same<TA, float>::value &&
-                  resident4_fits(128, M, kResB)) {
-        // four columns per lane (bit-identical results), unless two are asked for
-        if (g.ni == 128 && g.res_cols != 2) {
-            const size_t lds4 = resident4_lds_bytes(128, M);
-            auto f = k_resident4<R2, GAUSS>;
-            if (lds4 > kLdsBytes - 1024 ||
-                (lds4 > 64 * 1024 &&
-                 hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(kLdsBytes - 1024)) != hipSuccess))
-                return hipErrorInvalidValue;
-            hipLaunchKernelGGL(f, dim3((unsigned)g.nids), dim3(256), lds4, s, g.sd, g.ids, g.geo,
-                               (float *)state, nsteps, ooi);
-            return hipGetLastError();
-        }
-    }
     return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, false>)
                       : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, false>);
 }

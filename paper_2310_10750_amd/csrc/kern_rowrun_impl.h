@@ -126,6 +126,38 @@ __device__ __forceinline__ void row_windows(const TA *win, const TA *g, Acc &&ac
     });
 }
 
+// row_windows for C adjacent columns at once (column c's window is
+// win[c .. c + 2M]): the columns' window growth and accumulation are
+// interleaved, k by k, so that C independent chains are in flight; per column
+// the operations and their order are those of row_windows.  acc(dy, c) names
+// the accumulator of column c's output fed by disc row dy.
+template <int R2, bool GAUSS, int C, class TA, class Acc>
+__device__ __forceinline__ void row_windows_cols(const TA *win, const TA *g, Acc &&acc) {
+    using D = Disc<R2>;
+    constexpr int M = D::M;
+    TA H[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) H[c] = GAUSS ? g[0] * win[c + M] : win[c + M];
+    sfor<0, M + 1>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k > 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const TA pair = win[c + M - k] + win[c + M + k];
+                H[c] = GAUSS ? madd(g[k], pair, H[c]) : (H[c] + pair);
+            }
+        }
+        sfor<D::start[k], D::start[k + 1]>([&](auto E) {
+            constexpr int dy = D::dy_by_w[E];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                TA &r = acc(dy, c);
+                r = GAUSS ? madd(g[cabs(dy)], H[c], r) : (r + H[c]);
+            }
+        });
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Streaming step: a workgroup is one wave that owns a strip of 64R columns
 // and a band of B output rows of one sample.  It walks the B + 2m input rows
@@ -189,7 +221,7 @@ __global__ __launch_bounds__(64) void k_stream(
 #pragma unroll
     for (int k = 0; k < CPL; ++k) pre2[k] = src[(int64_t)gy * n + gxs[k]];
 
-    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    const TA ap = coef_ap<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
@@ -264,11 +296,11 @@ __global__ __launch_bounds__(64) void k_stream(
                     for (int c = 0; c < R; ++c) {
                         const int x = x0 + c0 + c;
                         const TA u = to_acc<TA>(cen[c]);
-                        const TA lsum = lsum_of(ce, u, acc[done][c]);
                         if (x < ne) {
-                            dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                            dst[(int64_t)y * n + x] =
+                                to_store<TS>(update_g<TA>(u, acc[done][c], ap, bcoef));
                             if (epart) {
-                                e_ul += u * lsum;
+                                e_ul += u * lsum_of(ce, u, acc[done][c]);
                                 e_pot += TA(1) - u * u;
                             }
                         }
@@ -363,7 +395,7 @@ __global__ __launch_bounds__(512) void k_band(
     const int s = wv * L;
     const int Lw = wv < weff - 1 ? L : T - s;
 
-    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    const TA ap = coef_ap<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
@@ -468,12 +500,11 @@ __global__ __launch_bounds__(512) void k_band(
                         for (int c = 0; c < R; ++c) {
                             const int x = x0 + c0 + c;
                             const TA u = to_acc<TA>(cen[c]);
-                            const TA lsum = lsum_of(ce, u, acc[done][c]);
                             if (x < ne) {
                                 dst[(int64_t)y * n + x] =
-                                    to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                                    to_store<TS>(update_g<TA>(u, acc[done][c], ap, bcoef));
                                 if (epart) {
-                                    e_ul += u * lsum;
+                                    e_ul += u * lsum_of(ce, u, acc[done][c]);
                                     e_pot += TA(1) - u * u;
                                 }
                             }
@@ -505,11 +536,10 @@ __global__ __launch_bounds__(512) void k_band(
                     const TA sum = acc[(k + 1) % P][c] +
                                    heads[((size_t)(wv + 1) * 2 * M + k) * TX + c0 + c];
                     const TA u = to_acc<TA>(src[(int64_t)y * n + xcl[c]]);
-                    const TA lsum = lsum_of(ce, u, sum);
                     if (x < ne) {
-                        dst[(int64_t)y * n + x] = to_store<TS>(update<TA>(u, lsum, a, bcoef));
+                        dst[(int64_t)y * n + x] = to_store<TS>(update_g<TA>(u, sum, ap, bcoef));
                         if (epart) {
-                            e_ul += u * lsum;
+                            e_ul += u * lsum_of(ce, u, sum);
                             e_pot += TA(1) - u * u;
                         }
                     }
@@ -636,7 +666,7 @@ __global__ __launch_bounds__(512, INPLACE ? 4 : 1) void k_resident(
     const int bup = band + 1 < NB ? band + 1 : 0;
     const int bdn = band > 0 ? band - 1 : NB - 1;
 
-    const TA a = coef_a<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    const TA ap = coef_ap<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
     TA g[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
@@ -833,14 +863,14 @@ __global__ __launch_bounds__(512, INPLACE ? 4 : 1) void k_resident(
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 const TA u = st[q][c];
-                const TA lsum = lsum_of(ce, u, acc[M + q][c]);
                 if constexpr (ENERGY) {
                     if (xb + c < n) {
+                        const TA lsum = lsum_of(ce, u, acc[M + q][c]);
                         e_ul += (double)u * (double)lsum;
                         e_pot += 1.0 - (double)u * (double)u;
                     }
                 }
-                st[q][c] = to_acc<TA>(to_store<TS>(update<TA>(u, lsum, a, bcoef)));
+                st[q][c] = to_acc<TA>(to_store<TS>(update_g<TA>(u, acc[M + q][c], ap, bcoef)));
             }
         if constexpr (ENERGY) {
             e_ul = block_sum(e_ul, red);
@@ -872,226 +902,5 @@ __global__ __launch_bounds__(512, INPLACE ? 4 : 1) void k_resident(
     }
 }
 
-
-// ---------------------------------------------------------------------------
-// LDS-resident kernel with four columns per lane (FP32 state and arithmetic,
-// n = 128, periodic).  The layout of k_resident, with two changes that cut
-// the LDS traffic of the row walk:
-//  * a lane owns 4 adjacent columns, so a row of 128 columns takes 32 lanes
-//    and one wave walks two bands (lanes 0-31 band 2w, lanes 32-63 band
-//    2w + 1; four waves hold the 8 bands of 16 rows);
-//  * the row stride is a multiple of 4 floats, so a lane's window of 2m + 4
-//    values, which starts at its first column minus m, is 16-byte aligned
-//    and read with 16-byte LDS loads (2m + 4 values for 4 sites instead of
-//    2m + 2 for 2).
-// Every site sums the same window sums in the same order as k_resident (own
-// rows in order, then the band above's partial sums, then the band below's),
-// so the two kernels give bit-identical states.  The partial sums are handed
-// over in place, in the band's own rows, as in k_resident.
-// ---------------------------------------------------------------------------
-
-// Row stride of the four-column layout: n plus the 2m halo, plus two columns
-// for odd m (the last lane's rounded-up window read), rounded up to 4 floats.
-__host__ __device__ constexpr int resident4_row_stride(int n, int M) {
-    return (n + 2 * M + (M % 2 ? 2 : 0) + 3) & ~3;
-}
-
-__host__ __device__ constexpr size_t resident4_lds_bytes(int n, int M) {
-    return (size_t)n * resident4_row_stride(n, M) * sizeof(float);
-}
-
-// Built where the partial sums of a band fit in its own rows.
-__host__ __device__ constexpr bool resident4_fits(int n, int M, int B) {
-    return n == 128 && M <= B && 2 * M * n <= B * resident4_row_stride(n, M);
-}
-
-template <int R2, bool GAUSS>
-__global__ __launch_bounds__(256, 2) void k_resident4(
-    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
-    const ModelGeo *__restrict__ geo, float *__restrict__ state, int nsteps,
-    double *__restrict__ ooi) {
-    constexpr int N = 128, R = 4, B = 16;
-    constexpr int M = Disc<R2>::M;
-    constexpr int WIN = 2 * M + R;
-    constexpr int WIN4 = (WIN + 3) / 4;  // 16-byte loads per window
-    constexpr int Q = B + 2 * M;         // outputs fed by one band: its rows +- m
-    constexpr int TW = resident4_row_stride(N, M);
-    constexpr int NB = N / B;
-    static_assert(resident4_fits(N, M, B), "partial sums must fit in the band's rows");
-    static_assert(TW % 4 == 0 && M + 4 * 31 + 4 * WIN4 - M <= TW, "aligned windows");
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[4];
-
-    float *lds = reinterpret_cast<float *>(smem_raw);
-    const int sidx = ids[blockIdx.x];
-    const SampleDesc d = sd[sidx];
-    float *g_state = state + d.offset;
-    const int lane = threadIdx.x & 63;
-    const int band = 2 * (threadIdx.x >> 6) + (lane >> 5);
-    const int xb = 4 * (lane & 31);  // this lane's columns xb .. xb + 3
-    const int y0 = band * B;
-    const int bup = band + 1 < NB ? band + 1 : 0;  // the band below (rows y0 + B ..)
-    const int bdn = band > 0 ? band - 1 : NB - 1;  // the band above
-
-    const float a = coef_a<float>(d), bcoef = coef_b<float>(d), ce = geo_ce<float>(geo);
-    float g[M + 1];
-#pragma unroll
-    for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<float>(geo, k) : 1.0f;
-
-    // Stores the 4 values of a lane at LDS element index i (i = row start +
-    // m + column): one 16-byte store when m is a multiple of 4, else two
-    // 8-byte or four 4-byte stores.
-    auto put4 = [&](int i, const float *v) {
-        if constexpr (M % 4 == 0) {
-            *reinterpret_cast<float4 *>(lds + i) = make_float4(v[0], v[1], v[2], v[3]);
-        } else if constexpr (M % 2 == 0) {
-            reinterpret_cast<float2 *>(lds + i)[0] = make_float2(v[0], v[1]);
-            reinterpret_cast<float2 *>(lds + i)[1] = make_float2(v[2], v[3]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) lds[i + c] = v[c];
-        }
-    };
-    auto get4 = [&](int i, float *v) {
-        if constexpr (M % 4 == 0) {
-            const float4 t = *reinterpret_cast<const float4 *>(lds + i);
-            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-        } else if constexpr (M % 2 == 0) {
-            const float2 t0 = reinterpret_cast<const float2 *>(lds + i)[0];
-            const float2 t1 = reinterpret_cast<const float2 *>(lds + i)[1];
-            v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = lds[i + c];
-        }
-    };
-
-    // Load and project u0 onto [-1, 1] (16-byte global loads, coalesced).
-    float st[B][R];
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-        const float4 t = *reinterpret_cast<const float4 *>(g_state + (int64_t)(y0 + q) * N + xb);
-        st[q][0] = clamp1(t.x);
-        st[q][1] = clamp1(t.y);
-        st[q][2] = clamp1(t.z);
-        st[q][3] = clamp1(t.w);
-    }
-
-    for (int step = 0; step < nsteps; ++step) {
-        // Publish the state; then the lanes at the lattice edge write the
-        // periodic column halo in stores of their own.
-#pragma unroll
-        for (int q = 0; q < B; ++q) put4((y0 + q) * TW + M + xb, st[q]);
-        if (xb < M || xb + 4 > N - M) {
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const int x = xb + c;
-                if (x < M || x >= N - M) {
-                    const int xh = x < M ? x + N : x - N;
-#pragma unroll
-                    for (int q = 0; q < B; ++q) lds[(y0 + q) * TW + M + xh] = st[q][c];
-                }
-            }
-        }
-        __syncthreads();
-
-        // acc[M + q] collects output row y0 + q, q in [-m, B + m).
-        float acc[Q][R];
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[q][c] = -0.0f;
-        const float *rp0 = lds + y0 * TW + xb;
-        float win[2][4 * WIN4];
-        auto load_win = [&](const float *p, float *w) {
-#pragma unroll
-            for (int j = 0; j < WIN4; ++j) {
-                const float4 t = reinterpret_cast<const float4 *>(p)[j];
-                w[4 * j] = t.x;
-                w[4 * j + 1] = t.y;
-                w[4 * j + 2] = t.z;
-                w[4 * j + 3] = t.w;
-            }
-        };
-        load_win(rp0, win[0]);
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            asm volatile("" ::: "memory");
-            if (i + 1 < B) load_win(rp0 + (i + 1) * TW, win[(i + 1) & 1]);
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                // input row i feeds output q = i - dy
-                row_windows<R2, GAUSS>(win[i & 1] + c, g, [&](int dy) -> float & {
-                    return acc[M + i - dy][c];
-                });
-            }
-        }
-        // Take the band's sites back into registers, then hand the
-        // overhanging partial sums over in the band's own rows (each half of
-        // a wave touches only its own band's rows, and one wave's LDS
-        // operations complete in order).
-#pragma unroll
-        for (int q = 0; q < B; ++q) get4((y0 + q) * TW + M + xb, st[q]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float *myup = lds + y0 * TW;
-        float *mydn = myup + M * N;
-        const float *above = lds + bdn * B * TW + M * N;
-        const float *below = lds + bup * B * TW;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            *reinterpret_cast<float4 *>(myup + j * N + xb) =
-                make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
-            *reinterpret_cast<float4 *>(mydn + j * N + xb) =
-                make_float4(acc[B + M + j][0], acc[B + M + j][1], acc[B + M + j][2],
-                            acc[B + M + j][3]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const float4 t = *reinterpret_cast<const float4 *>(above + j * N + xb);
-            acc[M + j][0] += t.x;
-            acc[M + j][1] += t.y;
-            acc[M + j][2] += t.z;
-            acc[M + j][3] += t.w;
-        }
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const float4 t = *reinterpret_cast<const float4 *>(below + j * N + xb);
-            acc[B + j][0] += t.x;
-            acc[B + j][1] += t.y;
-            acc[B + j][2] += t.z;
-            acc[B + j][3] += t.w;
-        }
-        // the neighbours have read this band's rows before it publishes the
-        // next state there
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < B; ++q)
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const float u = st[q][c];
-                const float lsum = lsum_of(ce, u, acc[M + q][c]);
-                st[q][c] = update<float>(u, lsum, a, bcoef);
-            }
-    }
-
-    // Write back and reduce the output of interest in FP64.
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-        *reinterpret_cast<float4 *>(g_state + (int64_t)(y0 + q) * N + xb) =
-            make_float4(st[q][0], st[q][1], st[q][2], st[q][3]);
-#pragma unroll
-        for (int c = 0; c < R; ++c) part += (double)st[q][c];
-    }
-    const double tot = block_sum(part, red);
-    if (threadIdx.x == 0) {
-        const double mean = tot / ((double)N * N);
-        ooi[2 * (int64_t)sidx] = mean;
-        ooi[2 * (int64_t)sidx + 1] = 0.5 * (1.0 + mean);
-    }
-}
 
 }  // namespace nlch

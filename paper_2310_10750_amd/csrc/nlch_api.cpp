@@ -276,6 +276,9 @@ void nlch::fill_sample_desc(const nlch_model &md, const ModelInfo &mi, const nlc
     d.b = c.b;
     d.af = rne_f32(c.a);
     d.bf = rne_f32(c.b);
+    // a - b ce with the kernels' unit-amplitude mass ce (separable form)
+    d.ap = c.c1 * (sm.c_F - sm.kernel_amp * mi.ce_sep / ((double)md.n * md.n));
+    d.apf = rne_f32(d.ap);
     const double h2 = 1.0 / ((double)md.n * md.n);
     d.e_int = 0.5 * h2 * h2 * sm.kernel_amp;
     d.e_pot = 0.5 * h2 * sm.c_F;
@@ -550,6 +553,7 @@ struct TuneVal {
 std::map<TuneKey, TuneVal> g_tuned;
 TuneVal g_force{0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods)
 int g_force_res_cols = 0;     // nlch_set_resident_shape
+int g_force_res_rows = 0;
 
 void set_shape(Group &g, const TuneVal &v) {
     g.tune_R = v.R;
@@ -859,8 +863,11 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         for (Group &g : b->groups) set_shape(g, {0, 0, 0, 0});
     }
 
-    for (size_t gi = 0; gi < b->groups.size(); ++gi)
-        b->groups[gi].res_cols = b->variant[gi] == kResident ? g_force_res_cols : 0;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const bool res = b->variant[gi] == kResident;
+        b->groups[gi].res_cols = res ? g_force_res_cols : 0;
+        b->groups[gi].res_rows = res ? g_force_res_rows : 0;
+    }
 
     if (energy_out) {
         rc = ensure_epart(*b);
@@ -888,6 +895,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         append_bytes(gk, g.tune_W);
         append_bytes(gk, g.tune_L);
         append_bytes(gk, g.res_cols);
+        append_bytes(gk, g.res_rows);
     }
     auto it = b->graphs.find(gk);
     if (it == b->graphs.end()) {
@@ -1038,11 +1046,14 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
     return NLCH_OK;
 }
 
-int nlch_set_resident_shape(int32_t cols_per_lane) {
-    if (!(cols_per_lane == 0 || cols_per_lane == 2 || cols_per_lane == 4))
-        return fail(NLCH_EINVAL, "columns per lane must be 0 (default), 2 or 4");
+int nlch_set_resident_shape(int32_t cols_per_lane, int32_t rows_per_lane) {
+    const int c = cols_per_lane, r = rows_per_lane;
+    if (!((c == 0 && r == 0) || (c == 2 && r == 16) || (c == 4 && (r == 16 || r == 8))))
+        return fail(NLCH_EINVAL, "resident shape must be (0, 0) (default), (2, 16), (4, 16) or "
+                    "(4, 8) columns and rows per lane");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_force_res_cols = cols_per_lane;
+    g_force_res_cols = c;
+    g_force_res_rows = r;
     return NLCH_OK;
 }
 

@@ -75,12 +75,31 @@ __device__ __forceinline__ TA lsum_of(TA ce, TA u, TA G) {
 }
 
 // v = u + (a u - b Lsum), projected.  Sign-symmetric: update(-u, -Lsum) is
-// -update(u, Lsum) exactly.
+// -update(u, Lsum) exactly.  (The per-site direct kernel, which forms Lsum
+// itself.)
 template <class TA>
 __device__ __forceinline__ TA update(TA u, TA lsum, TA a, TA b) {
     const TA t = madd(-b, lsum, a * u);
     return clamp1(u + t);
 }
+
+// The same update from the disc sum G (Lsum = ce u - G):
+//   a u - b Lsum = (a - b ce) u + b G = ap u + b G,  ap = c1 (c_F - c_gamma_h),
+// one fused multiply-add on the small term ap u (5 lane operations with the
+// projection instead of 6).  Sign-symmetric, and u = +-1, 0 stay fixed
+// exactly (for u = 1 the increment rounds to about a = c1 c_F > 0).
+template <class TA>
+__device__ __forceinline__ TA update_g(TA u, TA G, TA ap, TA b) {
+    const TA t = madd(b, G, ap * u);
+    return clamp1(u + t);
+}
+
+template <class TA>
+__device__ __forceinline__ TA coef_ap(const SampleDesc &d);
+template <>
+__device__ __forceinline__ float coef_ap<float>(const SampleDesc &d) { return d.apf; }
+template <>
+__device__ __forceinline__ double coef_ap<double>(const SampleDesc &d) { return d.ap; }
 
 // Periodic index for |i| < 2n.
 __device__ __forceinline__ int wrap_once(int i, int n) {

@@ -41,6 +41,8 @@ struct ModelGeo {
 // Energy factors: E_h(u) = e_int sum_i u_i Lsum_i + e_pot sum_i (1 - u_i^2)
 //   with e_int = h^4 amp / 2 and e_pot = h^2 c_F / 2.
 // xi = xi_h = c_gamma_h - c_F of the sample (used by the beta2 > 0 step).
+// ap = a - b ce = c1 (c_F - h^2 amp ce): the update as u + (ap u + b G) from
+// the unit-amplitude disc sum G = ce u - Lsum.
 struct SampleDesc {
     int64_t offset;   // element offset of the sample's n x n state
     int32_t model;
@@ -49,6 +51,8 @@ struct SampleDesc {
     float af, bf;
     double e_int, e_pot;
     double xi;
+    double ap;
+    float apf, pad;
 };
 
 // One launch group: samples of one model, processed by one kernel variant.
@@ -68,7 +72,8 @@ struct Group {
     int32_t tune_R, tune_B;  // streaming shape (0 = heuristic): columns per
     int32_t tune_W, tune_L;  //   lane, band rows, waves per band, rows per wave
     int32_t ta_bytes;        // size of the arithmetic type (4 or 8)
-    int32_t res_cols;        // resident kernel: columns per lane (0 = default)
+    int32_t res_cols;        // resident kernel: columns per lane and rows each
+    int32_t res_rows;        //   lane walks (0 = default)
 };
 
 // Heuristic streaming shape of the row-run kernel: lanes own R columns of a
@@ -169,6 +174,11 @@ bool resident_supported(int prec, bool acc64, int R2, int kernel, int n, bool vo
 hipError_t launch_resident(int prec, bool acc64, const Group &g, void *state,
                            int nsteps, double *ooi, hipStream_t s,
                            double *energy = nullptr, int64_t estride = 0);
+// The resident kernels with four columns per lane (FP32 state, n = 128,
+// periodic): built for these discs.  energy (nullable) as in launch_resident.
+bool resident4_built(int R2);
+hipError_t resident4_launch_f32(const Group &g, void *state, int nsteps, double *ooi,
+                                hipStream_t s, double *energy, int64_t estride);
 // One beta2 > 0 step of every sample of the group (one workgroup per sample,
 // workspace g.ws); epart (nullable) receives one energy partial pair per
 // sample.  warm: start Newton from the z the workspace holds (the previous

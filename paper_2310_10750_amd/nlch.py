@@ -115,7 +115,7 @@ def load():
     lib.nlch_solve_batch_energy.restype = ctypes.c_int
     lib.nlch_set_stream_shape.argtypes = [i32, i32, i32, i32]
     lib.nlch_set_stream_shape.restype = ctypes.c_int
-    lib.nlch_set_resident_shape.argtypes = [i32]
+    lib.nlch_set_resident_shape.argtypes = [i32, i32]
     lib.nlch_set_resident_shape.restype = ctypes.c_int
     lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64,
                                   pd, ctypes.POINTER(mfmc_result), vp]
@@ -247,8 +247,8 @@ def nlch_set_stream_shape(R=0, W=0, periods=0, B=0) -> None:
     _check(load().nlch_set_stream_shape(R, W, periods, B))
 
 
-def nlch_set_resident_shape(cols_per_lane=0) -> None:
-    _check(load().nlch_set_resident_shape(int(cols_per_lane)))
+def nlch_set_resident_shape(cols_per_lane=0, rows_per_lane=0) -> None:
+    _check(load().nlch_set_resident_shape(int(cols_per_lane), int(rows_per_lane)))
 
 
 def mfmc_estimate(ys, m, alpha=None, stream=None, y_stride=1) -> dict:

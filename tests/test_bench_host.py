@@ -14,33 +14,53 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-@pytest.mark.parametrize("m,ops", [(0, 7), (1, 11), (8, 39), (32, 135)])
-def test_algorithmic_ops_is_4m_plus_7(m, ops):
-    # 2m window terms, 2m+1 row sums, 6 for the update and projection
+@pytest.mark.parametrize("m,ops", [(0, 6), (1, 10), (8, 38), (32, 134)])
+def test_algorithmic_ops_is_4m_plus_6(m, ops):
+    # 2m window terms, 2m+1 row sums, 5 for the update and projection
     assert bench.algorithmic_ops(m, 0) == ops
     assert bench.algorithmic_ops(m, 1) == ops
 
 
+@pytest.mark.parametrize("m", [0, 1, 8, 32])
+def test_algorithmic_flops(m):
+    # constant kernel: adds only, plus mul, fma (2), add in the update
+    assert bench.algorithmic_flops(m, 0) == 4 * m + 5
+    # Gaussian: m of the window terms and the 2m+1 row sums are fmas
+    assert bench.algorithmic_flops(m, 1) == 7 * m + 6
+
+
+def test_roofline_labels_in_source():
+    """The roofline object names its unit in lane-operations, carries the
+    FLOP-based fraction against the published 157.3 TFLOP/s, the LDS
+    fractions against both measured read rates and the binding pipe."""
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for key in ('"unit": "T lane-ops/s"', '"frac_flops"', '"peak_tflops": FP32_PEAK_TFLOPS',
+                '"frac_measured_8B"', '"frac_measured_16B"', '"binding_pipe"'):
+        assert key in src, key
+    assert bench.FP32_PEAK_TFLOPS == 157.3
+    assert abs(bench.VALU_PEAK_TOPS - 78.6432) < 1e-3
+
+
 def test_source_hash_tracks_the_kernel_sources(tmp_path, monkeypatch):
-    h = bench.kernel_source_hash("k_resident")
+    h = bench.kernel_source_hash("k_resident4h")
     assert len(h) == 16 and int(h, 16) >= 0
-    assert bench.kernel_source_hash("k_resident") == h
+    assert bench.kernel_source_hash("k_resident4h") == h
     # a copy of the sources with one byte changed hashes differently
     csrc = os.path.join(ROOT, "paper_2310_10750_amd", "csrc")
     fake = tmp_path / "paper_2310_10750_amd" / "csrc"
     fake.mkdir(parents=True)
-    for f in bench.KERNEL_SOURCES["k_resident"]:
+    for f in bench.KERNEL_SOURCES["k_resident4h"]:
         data = open(os.path.join(csrc, f), "rb").read()
         if f == "kern_rowrun_impl.h":
             data += b"\n"
         (fake / f).write_bytes(data)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.kernel_source_hash("k_resident") != h
+    assert bench.kernel_source_hash("k_resident4h") != h
 
 
 def test_stored_counters_are_consistent():
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    e = d["k_resident"]
+    e = d["k_resident4h"]
     assert e["bytes_per_launch"] == pytest.approx(e["fetch_bytes"] + e["write_bytes"], abs=2)
     assert e["algorithmic_bytes"] == 2 * 4096 * 128 * 128 * 4
     # HBM: within a few percent of reading and writing each state once
@@ -50,18 +70,18 @@ def test_stored_counters_are_consistent():
 
 
 def test_stored_counters_only_for_their_workload_and_sources(monkeypatch):
-    e = bench.stored_counters("k_resident", "C3")
-    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_resident"]
-    if d["source_hash"] == bench.kernel_source_hash("k_resident"):
+    e = bench.stored_counters("k_resident4h", "C3")
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_resident4h"]
+    if d["source_hash"] == bench.kernel_source_hash("k_resident4h"):
         assert e is not None and e["bytes_per_launch"] == d["bytes_per_launch"]
-        assert bench.stored_traffic("k_resident", "C3") == d["bytes_per_launch"]
+        assert bench.stored_traffic("k_resident4h", "C3") == d["bytes_per_launch"]
     else:
         assert e is None
-    assert bench.stored_counters("k_resident", "V3") is None
+    assert bench.stored_counters("k_resident4h", "V3") is None
     assert bench.stored_counters("k_rowrun", "C3") is None
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda k="k_resident": "0" * 16)
-    assert bench.stored_counters("k_resident", "C3") is None
-    assert bench.stored_traffic("k_resident", "C3") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k="k_resident4h": "0" * 16)
+    assert bench.stored_counters("k_resident4h", "C3") is None
+    assert bench.stored_traffic("k_resident4h", "C3") is None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -1,10 +1,17 @@
-"""The LDS-resident kernel's layouts give bit-identical states: two columns
-per lane with one 16-row band per wave, and four columns per lane with two
-bands per wave and 16-byte window loads (FP32, 128^2).  Every site sums the
-same window sums in the same order in both.  The outputs of interest are
-FP64 sums of the same values in a different order, so they agree to FP64
-rounding.  The oracle comparison of every built resident kernel at every site
-is in test_gpu_parity.py."""
+"""Layouts of the LDS-resident kernel (FP32, 128^2), set with
+nlch_set_resident_shape(columns, rows per lane):
+
+* (2, 16): two columns per lane, one 16-row band per wave;
+* (4, 16): four columns per lane, two bands per wave, 16-byte window loads.
+  Every site sums the same window sums in the same order as in (2, 16), so
+  the states are bit-identical;
+* (4, 8): one band per wave, each half-wave walking 8 rows.  Each band sum
+  is formed in two parts, so it differs from (2, 16) by FP32 rounding.  It
+  is checked against the FP64 oracle at every site, and against (2, 16)
+  along a trajectory.
+
+The outputs of interest are FP64 sums of the states in a layout-dependent
+order, so for bit-identical states they agree to FP64 rounding."""
 import math
 
 import numpy as np
@@ -17,12 +24,13 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
+SHAPES = [(2, 16), (4, 16), (4, 8)]
 
 
 @pytest.fixture(autouse=True)
 def _default_layout():
     yield
-    nlch.nlch_set_resident_shape(0)
+    nlch.nlch_set_resident_shape(0, 0)
 
 
 def _model(n, R2, kind, tau=0.05):
@@ -36,8 +44,8 @@ def _model(n, R2, kind, tau=0.05):
     return nlch.make_model(n, delta, kind, amp, sigma, tau=tau)
 
 
-def _solve(md, smp, host, nsteps, cols):
-    nlch.nlch_set_resident_shape(cols)
+def _solve(md, smp, host, nsteps, shape):
+    nlch.nlch_set_resident_shape(*shape)
     x = torch.from_numpy(host).to(DEV)
     ooi = torch.zeros(2 * len(smp), dtype=torch.float64, device=DEV)
     nlch.nlch_solve_batch([md], smp, nsteps, nlch.NLCH_F32, nlch.NLCH_ALGO_RESIDENT, x, None,
@@ -48,7 +56,7 @@ def _solve(md, smp, host, nsteps, cols):
 
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("R2", [1, 4, 9, 16, 25, 64])
-def test_four_columns_equal_two_columns(R2, kind):
+def test_layouts_of_the_resident_kernel(orc, R2, kind):
     print("layouts R2=%d kernel=%d" % (R2, kind), flush=True)
     n, S = 128, 5
     md = _model(n, R2, kind)
@@ -56,23 +64,44 @@ def test_four_columns_equal_two_columns(R2, kind):
     host = rng.uniform(-1.2, 1.2, S * n * n).astype(np.float32)
     smp = [nlch.nlch_sample(0, 0, 0.96 + 0.02 * k, md.kernel_amp, k * n * n) for k in range(S)]
     for nsteps in (0, 1, 7, 40):
-        s2, o2 = _solve(md, smp, host, nsteps, 2)
-        s4, o4 = _solve(md, smp, host, nsteps, 4)
+        out = {sh: _solve(md, smp, host, nsteps, sh) for sh in SHAPES}
+        s2, o2 = out[(2, 16)]
+        s4, o4 = out[(4, 16)]
+        sh8, oh8 = out[(4, 8)]
         assert np.array_equal(s2, s4), nsteps
         np.testing.assert_allclose(o4, o2, rtol=0, atol=1e-15)
+        # the split-band layout: FP32 rounding of the band sums, growing along
+        # the trajectory; each state's mean is its output of interest
+        assert np.max(np.abs(sh8.astype(np.float64) - s2)) <= (1e-6 if nsteps <= 1 else 1e-4)
+        for k in range(S):
+            assert abs(oh8[2 * k] - np.mean(sh8[k * n * n:(k + 1) * n * n].astype(np.float64))) \
+                <= 1e-12
+        if nsteps == 1:
+            # every site against the FP64 oracle
+            for k in range(S):
+                u0 = np.clip(host[k * n * n:(k + 1) * n * n].astype(np.float64), -1, 1)
+                ref = orc.step(u0.reshape(n, n), n, md.delta, md.kernel, md.kernel_amp,
+                               md.kernel_sigma, smp[k].c_F, md.beta1, md.tau)
+                got = sh8[k * n * n:(k + 1) * n * n].astype(np.float64).reshape(n, n)
+                assert np.max(np.abs(got - ref)) <= 1e-6
 
 
-def test_benchmark_workload_layouts_agree():
+def test_benchmark_workload_layouts_agree(orc):
     """256 samples of the benchmark workload (128^2, 197-point disc, per-sample
-    c_F, 500 steps): the two layouts give the same final states."""
+    c_F, 500 steps): (2, 16) and (4, 16) give the same states; (4, 8) meets
+    the OoI bar against the FP64 oracle."""
     print("C3 layouts", flush=True)
     w = synth.workload("C3", n_samples=256)
-    out = []
-    for cols in (2, 4):
-        nlch.nlch_set_resident_shape(cols)
+    out = {}
+    for sh in SHAPES:
+        nlch.nlch_set_resident_shape(*sh)
         b = DeviceBatch(w)
         b.solve(algo=nlch.NLCH_ALGO_AUTO)
         torch.cuda.synchronize()
-        out.append((b.state.cpu().numpy(), b.ooi_host()))
-    assert np.array_equal(out[0][0], out[1][0])
-    np.testing.assert_allclose(out[1][1], out[0][1], rtol=0, atol=1e-15)
+        out[sh] = (b.state.cpu().numpy(), b.ooi_host())
+    assert np.array_equal(out[(2, 16)][0], out[(4, 16)][0])
+    np.testing.assert_allclose(out[(4, 16)][1], out[(2, 16)][1], rtol=0, atol=1e-15)
+    from tests.gpu_harness import oracle_samples
+    ref = oracle_samples(orc, w, [0, 1, 255], "f32")
+    for i in (0, 1, 255):
+        assert abs(out[(4, 8)][1][i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2])
