@@ -54,8 +54,12 @@ bool resident_supported(int prec, bool acc64, int R2, int, int n, bool vol) {
     }
 }
 
-hipError_t launch_rowrun_step(int prec, bool, const Group &g, const void *in, void *out,
+hipError_t launch_rowrun_step(int prec, bool acc64, const Group &g, const void *in, void *out,
                               hipStream_t s, double *epart) {
+    // the tiled kernel has no energy partials: the trace keeps the streaming
+    // kernel, whose states are the same bit for bit
+    if (g.tile && !epart && tile_supported(prec, acc64, g.R2))
+        return launch_tile_step(prec, g, in, out, s);
     switch (prec) {
         case kF64: return rowrun_step_f64(g, in, out, s, epart);
         case kF32: return rowrun_step_f32(g, in, out, s, epart);
@@ -555,11 +559,23 @@ TuneVal g_force{0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods)
 int g_force_res_cols = 0;     // nlch_set_resident_shape
 int g_force_res_rows = 0;
 
+// Default for R = 0: the tiled kernel where the default streaming shape
+// (one wave per band) would give fewer than 1024 waves in all, i.e. for one
+// or a few samples of a lattice; R = 4 asks for it.
 void set_shape(Group &g, const TuneVal &v) {
-    g.tune_R = v.R;
+    g.tune_R = v.R == 4 ? 0 : v.R;
     g.tune_B = v.B;
     g.tune_W = v.W;
     g.tune_L = v.L;
+    const bool built = tile_supported(g.ta_bytes == 8 ? kF64 : kF32, g.ta_bytes == 8, g.R2);
+    if (v.R == 4) {
+        g.tile = built;
+    } else if (v.R == 0 && v.W == 0 && v.B == 0) {
+        const StreamShape sh = stream_shape(g);
+        g.tile = built && (int64_t)sh.per_sample * g.nids < 1024;
+    } else {
+        g.tile = 0;
+    }
 }
 
 int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void *out,
@@ -581,6 +597,7 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
             if (waves >= 128 || Bc == bmin || Bc == g.ni) cands.push_back({R, Bc, 1, 0});
             if (Bc >= g.ni) break;
         }
+        if (R == 1 && tile_supported(prec, acc64, g.R2)) cands.push_back({4, 0, 0, 0});
         for (int W = 2; W <= 8 && band_built(g.m, g.ta_bytes); W *= 2)
             for (int k = 1; k <= 4; k *= 2) {
                 const int L = k * P;
@@ -753,6 +770,8 @@ int enqueue_solve(Batch &b, DevCtx &ctx, int prec, bool acc64, int nsteps, void 
 
 }  // namespace
 
+void nlch::set_default_shape(Group &g) { set_shape(g, {0, 0, 0, 0}); }
+
 // nlch_solve_batch and nlch_solve_batch_energy (energy_out nullable here).
 static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sample *samples,
                       int64_t n_samples, int32_t nsteps, int32_t precision, int32_t algo,
@@ -896,6 +915,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         append_bytes(gk, g.tune_L);
         append_bytes(gk, g.res_cols);
         append_bytes(gk, g.res_rows);
+        append_bytes(gk, g.tile);
     }
     auto it = b->graphs.find(gk);
     if (it == b->graphs.end()) {
@@ -1028,7 +1048,8 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
     bool capturing = false;
     rc = batch_begin(*b, s, &capturing);
     if (rc) return rc;
-    const Group &g = b->groups[0];
+    Group &g = b->groups[0];
+    set_shape(g, {0, 0, 0, 0});  // the default shape (tiled for one sample where built)
     // the step writes the updated block only; the fixed ring is carried over
     if (g.lo != 0) HIP_TRY(launch_project(precision, g, u_in, u_out, s));
     HIP_TRY(launch_step(b->variant[0], precision, acc64, g, u_in, u_out, s));
@@ -1037,10 +1058,10 @@ int nlch_step(const nlch_model *model, int32_t precision, int32_t algo, const vo
 }
 
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
-    if (R < 0 || R > 2 || !(W == 0 || W == 1 || W == 2 || W == 4 || W == 8) || periods < 0 ||
-        periods > 64 || B < 0)
-        return fail(NLCH_EINVAL, "bad streaming shape (R in 0..2, W in {0,1,2,4,8}, "
-                                 "periods 0..64, B >= 0)");
+    if (!(R == 0 || R == 1 || R == 2 || R == 4) || !(W == 0 || W == 1 || W == 2 || W == 4 || W == 8) ||
+        periods < 0 || periods > 64 || B < 0 || (R == 4 && (W > 1 || periods || B)))
+        return fail(NLCH_EINVAL, "bad streaming shape (R in {0,1,2,4}, W in {0,1,2,4,8}, "
+                                 "periods 0..64, B >= 0; R = 4 takes no other field)");
     std::lock_guard<std::mutex> lk(g_mu);
     g_force = {R, B, W, periods};
     return NLCH_OK;

@@ -71,4 +71,8 @@ Group make_group(const nlch_model &md, const ModelInfo &mi, int model_index, int
 
 size_t prec_size(int prec);
 
+// The default launch shape of a row-run group (the tiled kernel for one or
+// a few samples where it is built, else one wave per band).
+void set_default_shape(Group &g);
+
 }  // namespace nlch

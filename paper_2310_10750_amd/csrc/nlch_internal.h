@@ -74,6 +74,7 @@ struct Group {
     int32_t ta_bytes;        // size of the arithmetic type (4 or 8)
     int32_t res_cols;        // resident kernel: columns per lane and rows each
     int32_t res_rows;        //   lane walks (0 = default)
+    int32_t tile;            // row-run steps on 32 x 32 output tiles (k_tile)
 };
 
 // Heuristic streaming shape of the row-run kernel: lanes own R columns of a
@@ -119,6 +120,13 @@ inline size_t stream_lds_bytes(int R, int M, int W, int ta_bytes) {
 // Shared-band kernels are built for FP32 arithmetic and horizons m <= 16 (for
 // wider discs the 2m rows of partial sums per wave limit occupancy too much).
 constexpr bool band_built(int M, int ta_bytes) { return ta_bytes == 4 && M <= 16; }
+
+// Tiled one-step kernel (k_tile, FP32 arithmetic, m <= 16): built for a disc,
+// workgroups one sample takes, launch (one step of every sample).
+bool tile_supported(int prec, bool acc64, int R2);
+int tile_blocks_per_sample(int ni);
+hipError_t launch_tile_step(int prec, const Group &g, const void *in, void *out,
+                            hipStream_t s);
 
 inline StreamShape stream_shape(const Group &g) {
     StreamShape sh;

@@ -186,6 +186,7 @@ extern "C" int nlch_step_noalloc(const nlch_model *model, int32_t precision, int
     g.ewf = reinterpret_cast<const float *>(ab + off_ewf);
     g.partial = reinterpret_cast<double *>(ab + off_part);
     g.ws = nullptr;
+    set_default_shape(g);  // as nlch_step
     // the step writes the updated block only; the fixed ring is carried over
     if (g.lo != 0) HIP_TRY(launch_project(precision, g, u_in, u_out, s));
     if (direct)
