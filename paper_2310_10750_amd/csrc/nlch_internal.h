@@ -117,9 +117,10 @@ inline size_t stream_lds_bytes(int R, int M, int W, int ta_bytes) {
     return (size_t)W * (ring + head) * ta_bytes;
 }
 
-// Shared-band kernels are built for FP32 arithmetic and horizons m <= 16 (for
-// wider discs the 2m rows of partial sums per wave limit occupancy too much).
-constexpr bool band_built(int M, int ta_bytes) { return ta_bytes == 4 && M <= 16; }
+// Shared-band kernels are built for FP32 arithmetic and horizons m <= 32 (the
+// 2m rows of partial sums per wave: 4 waves of one column per lane take
+// 70 KB of LDS at m = 32).
+constexpr bool band_built(int M, int ta_bytes) { return ta_bytes == 4 && M <= 32; }
 
 // Tiled one-step kernel (k_tile, FP32 arithmetic, m <= 16): built for a disc,
 // workgroups one sample takes, launch (one step of every sample).

@@ -296,16 +296,19 @@ def _shape_workload(prec="f32", nsteps=9, big=True):
               synth.Model(300, 16 / 300, 0, 1.0253 * 300 * 300 / 797, 0.0, tau=0.01),
               synth.Model(130, 32 / 130, 1, 4e-3 / (math.pi * (32 / 390) ** 4),
                           32 / 390, tau=0.01),
+              # m = 32 on a lattice of several ragged shared bands
+              synth.Model(400, 32 / 400, 0, 1.0253 * 400 * 400 / 3209, 0.0, tau=0.01),
               synth.Model(1024, 1 / 32, 1, amp, sigma, tau=0.01)]
     samples = [synth.Sample(0, 1.0, amp, "nuclei", 4, s, synth.draw_theta(synth.rng_for(4, s)))
                for s in range(3)]
     samples += [synth.Sample(1, 1.0, models[1].amp, "iid", 7, s) for s in range(2)]
     samples += [synth.Sample(2, 1.0, models[2].amp, "iid", 8, s) for s in range(2)]
+    samples += [synth.Sample(3, 1.0, models[3].amp, "iid", 9, 0)]
     if big:
-        samples += [synth.Sample(3, 1.0, amp, "nuclei", 4, 9,
+        samples += [synth.Sample(4, 1.0, amp, "nuclei", 4, 9,
                                  synth.draw_theta(synth.rng_for(4, 9)))]
     else:
-        models = models[:3]
+        models = models[:4]
     return synth.Workload("shapes", models, samples, nsteps, prec)
 
 
@@ -342,8 +345,9 @@ def test_multiwave_bands_one_step(orc, reset_shape, R, W, k, prec):
     """Bands shared by W waves (partial sums handed over in LDS): one step
     from random states against the oracle on every site, lattices with ragged
     strips and bands (300^2), a band taller than the lattice, and groups the
-    shared-band kernel is not built for (FP64; 130^2 with m = 32), which use
-    one wave per band; with the energy trace on."""
+    shared-band kernel is not built for (FP64), which use one wave per band;
+    m = 32 on 130^2 (one band) and 400^2 (ragged bands); with the energy
+    trace on."""
     w = _shape_workload(prec, nsteps=1, big=False)
     print("multiwave R=%d W=%d periods=%d %s" % (R, W, k, prec), flush=True)
     nlch.nlch_set_stream_shape(R, W, k, 0)
