@@ -32,6 +32,28 @@ Phi(z) = tau/2 z'Az + sum_i phi(z_i) - r'z with phi(s) = s^2/(2 xi) for
   solved by accelerated projected gradient with a dense A^{-1}: an
   independent method for cross-checking on tiny lattices.
 * multiplier: mu = A^{-1}(r - u)/tau - xi u, for the KKT checks.
+
+For xi <= 0 the term xi u of the potential's derivative is concave, and the
+literal step minimises a function that is not convex once
+xi < -1/(tau lambda_max(A)), so it may have several solutions.  Reading used
+(convex splitting applied to the paper's implicit/explicit split): xi u is
+implicit where it is convex (xi > 0, above) and taken at the previous step
+where it is concave (xi <= 0):
+
+    u + tau A mu = r',   r' = u_old + tau A (g - xi u_old),   mu in N_K(u),
+
+a strictly convex problem (u is the A^{-1}-weighted projection of r' onto K)
+with a unique solution.
+
+* step_b2_split: that step by a primal-dual active-set iteration on the
+  complementarity problem in mu (matrix tau A, an M-matrix): with
+  A+ = {mu + c (u - 1) > 0}, A- = {mu + c (u + 1) < 0}, u = +-1 there, mu = 0
+  elsewhere, solve tau A_AA mu_A = r'_A - u_A and u_I = r'_I - tau A_IA mu_A;
+  repeat until the active sets repeat (finite for M-matrices).
+* step_b2_qp(..., split=True): the same step as the box QP
+  min 1/2 u'(A^{-1}/tau)u - c'u, c = A^{-1} u_old/tau + g - xi u_old, by
+  accelerated projected gradient (independent solver, tiny lattices).
+* step_b2_any: the step for either sign of xi.
 """
 from __future__ import annotations
 
@@ -97,16 +119,59 @@ def step_b2(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, z0=None,
     raise RuntimeError("semismooth Newton did not converge")
 
 
-def step_b2_qp(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, iters=200000,
-               tol=1e-14):
-    """The same step as a box-constrained QP in u, by accelerated projected
-    gradient (FISTA) with dense matrices (tiny lattices only)."""
+def step_b2_split(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, c=1.0,
+                  max_iter=200):
+    """One step for xi <= 0 (xi u at the previous step; see the module
+    docstring) by the primal-dual active-set iteration.  Returns
+    (u, mu, iterations)."""
     _, xi, _ = constants(n, delta, kind, amp, sigma, c_F)
-    Ainv = np.linalg.inv(a_matrix(n, beta1, beta2).toarray())
-    M = Ainv / tau + xi * np.eye(n * n)
+    if xi > 0:
+        raise ValueError("the split step is the reading for xi <= 0 (xi = %g)" % xi)
+    A = a_matrix(n, beta1, beta2)
     u_old = np.asarray(u_old, dtype=np.float64).reshape(-1)
     g = convolve(u_old.reshape(n, n), n, delta, kind, amp, sigma).reshape(-1)
-    c = Ainv @ u_old / tau + g
+    rp = u_old + tau * (A @ (g - xi * u_old))
+    u, mu = rp.copy(), np.zeros_like(rp)
+    prev = None
+    for it in range(max_iter):
+        up = mu + c * (u - 1.0) > 0
+        dn = mu + c * (u + 1.0) < 0
+        key = (up.tobytes(), dn.tobytes())
+        if key == prev:
+            return u.reshape(n, n), mu.reshape(n, n), it
+        prev = key
+        act = up | dn
+        u = np.where(up, 1.0, np.where(dn, -1.0, u))
+        mu = np.zeros_like(rp)
+        if act.any():
+            Aa = (tau * A[act][:, act]).tocsc()
+            mu[act] = spla.spsolve(Aa, rp[act] - u[act])
+        inact = ~act
+        u[inact] = rp[inact] - tau * (A[inact][:, act] @ mu[act])
+    raise RuntimeError("active-set iteration did not settle")
+
+
+def step_b2_any(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, z0=None):
+    """The step for either sign of xi: (u, z or None)."""
+    _, xi, _ = constants(n, delta, kind, amp, sigma, c_F)
+    if xi > 0:
+        u, z, _ = step_b2(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, z0=z0)
+        return u, z
+    u, _, _ = step_b2_split(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau)
+    return u, None
+
+
+def step_b2_qp(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, iters=200000,
+               tol=1e-14, split=False):
+    """The same step as a box-constrained QP in u, by accelerated projected
+    gradient (FISTA) with dense matrices (tiny lattices only); split=True:
+    the xi <= 0 step (xi u at the previous step)."""
+    _, xi, _ = constants(n, delta, kind, amp, sigma, c_F)
+    Ainv = np.linalg.inv(a_matrix(n, beta1, beta2).toarray())
+    M = Ainv / tau + (0.0 if split else xi) * np.eye(n * n)
+    u_old = np.asarray(u_old, dtype=np.float64).reshape(-1)
+    g = convolve(u_old.reshape(n, n), n, delta, kind, amp, sigma).reshape(-1)
+    c = Ainv @ u_old / tau + g - (xi * u_old if split else 0.0)
     ev = np.linalg.eigvalsh(M)
     if ev[0] <= 0:
         raise ValueError("M is not positive definite: the step is not a convex QP")
@@ -125,22 +190,26 @@ def step_b2_qp(u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, iters=
 
 
 def multiplier(u_new, u_old, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau):
-    """mu of the step equation, mu = A^{-1}(r - u)/tau - xi u."""
+    """mu of the step equation: mu = A^{-1}(r - u)/tau - xi u (xi > 0), or
+    mu = A^{-1}(r' - u)/tau with r' = u_old + tau A (g - xi u_old) (xi <= 0)."""
     _, xi, _ = constants(n, delta, kind, amp, sigma, c_F)
     A = a_matrix(n, beta1, beta2)
     u_old = np.asarray(u_old, dtype=np.float64).reshape(-1)
     u = np.asarray(u_new, dtype=np.float64).reshape(-1)
     g = convolve(u_old.reshape(n, n), n, delta, kind, amp, sigma).reshape(-1)
-    r = u_old + tau * (A @ g)
-    return (spla.spsolve(A.tocsc(), r - u) / tau - xi * u).reshape(n, n)
+    if xi > 0:
+        r = u_old + tau * (A @ g)
+        return (spla.spsolve(A.tocsc(), r - u) / tau - xi * u).reshape(n, n)
+    rp = u_old + tau * (A @ (g - xi * u_old))
+    return (spla.spsolve(A.tocsc(), rp - u) / tau).reshape(n, n)
 
 
 def solve_b2(u0, nsteps, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau):
-    """Project u0 onto K and take nsteps steps (each warm-started from the
-    previous z).  Returns (u, mean, f1)."""
+    """Project u0 onto K and take nsteps steps (for xi > 0 each Newton
+    iteration warm-started from the previous z).  Returns (u, mean, f1)."""
     u = np.clip(np.asarray(u0, dtype=np.float64).reshape(n, n), -1.0, 1.0)
     z = None
     for _ in range(nsteps):
-        u, z, _ = step_b2(u, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, z0=z)
+        u, z = step_b2_any(u, n, delta, kind, amp, sigma, c_F, beta1, beta2, tau, z0=z)
     mean = float(np.sum(u) / (n * n))
     return u, mean, 0.5 * (1.0 + mean)
