@@ -30,15 +30,22 @@
  * by semismooth Newton with Jacobi-preconditioned conjugate-gradient inner
  * solves (one workgroup per sample, n <= 256; the Newton residual and its
  * convergence test are FP64, the on-chip variant for n = 64, 88, 128 keeps
- * the CG direction in FP32 and the CG solution as an FP32 pair).  Models with beta2 > 0 and a sample with
- * xi_h <= 0 (a non-convex step with possibly several solutions) are
- * NLCH_EUNSUPPORTED.  A sample whose Newton iteration does not converge
- * within its iteration cap gets a NaN state and output of interest.
+ * the CG direction in FP32 and the CG solution as an FP32 pair).  For
+ * xi_h <= 0 the term xi_h u is concave, and the literal step may have
+ * several solutions; the library then takes it at the previous step (convex
+ * splitting):
+ *     u + tau A mu = u^{k-1} + tau A (gamma*u^{k-1} - xi_h u^{k-1}),
+ * whose unique solution is found by a primal-dual active-set iteration with
+ * conjugate-gradient solves on the active rows of tau A (same layouts and
+ * precisions; converged when the active sets repeat and the FP64 residual of
+ * the active rows is below 1e-13 max(1, |right-hand side|)).  A batch may mix
+ * both signs.  A sample whose Newton (or active-set) iteration does not
+ * converge within its iteration cap gets a NaN state and output of interest.
  * Per sample the library keeps 7 n^2 doubles of workspace with the batch;
- * within one nlch_solve_batch call Newton starts each step from the previous
- * step's z held there (from xi_h u at the call's first step), so a solve split
- * over several calls agrees with one call to the Newton tolerance (~1e-13
- * relative), not bit for bit.
+ * within one nlch_solve_batch call each step starts from the previous step's
+ * z (xi_h > 0) or mu (xi_h <= 0) held there (from xi_h u, or from mu = 0, at
+ * the call's first step), so a solve split over several calls agrees with one
+ * call to the solver tolerance (~1e-13 relative), not bit for bit.
  *
  * Bounded domain (NLCH_BOUNDARY_VOLUME; Sec. 2.1: the operator integrates
  * over Omega = (0,1)^2 together with the interaction region Omega_I of points
@@ -146,8 +153,8 @@ typedef struct nlch_model {
     double kernel_sigma; /* Gaussian width > 0 (ignored for the constant kernel)*/
     double c_F;          /* obstacle-potential constant > 0                     */
     double beta1;        /* > 0                                                 */
-    double beta2;        /* >= 0; > 0 needs n <= 256 and xi_h > 0 per sample   */
-    double tau;          /* time step > 0 with 1 + tau beta1 xi_h > 0           */
+    double beta2;        /* >= 0; > 0 needs n <= 256 (either sign of xi_h)     */
+    double tau;          /* time step > 0; with beta2 = 0, 1 + tau beta1 xi_h > 0 */
     int32_t boundary;    /* NLCH_BOUNDARY_*                                     */
     int32_t reserved;    /* must be 0                                           */
 } nlch_model;
@@ -185,7 +192,9 @@ int nlch_disc(int32_t n, double delta, int64_t *R2, int32_t *m, int64_t *N,
 
 /* Discrete model constants (host only): c_gamma_h (kernel mass with the self
  * term), xi_h = c_gamma_h - c_F and c1 = tau beta1 / (1 + tau beta1 xi_h), for
- * the model's own c_F and amplitude.  Any output pointer may be NULL.
+ * the model's own c_F and amplitude (c1 = 0 for a beta2 > 0 model with
+ * 1 + tau beta1 xi_h <= 0, whose step does not use it).  Any output pointer
+ * may be NULL.
  * NLCH_EINVAL if the model is invalid (see nlch_model). */
 int nlch_model_constants(const nlch_model *model, double *c_gamma_h,
                          double *xi_h, double *c1);
@@ -277,6 +286,11 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
  * groups with FP32 arithmetic and m <= 16 (others use W = 1); a group whose
  * partial-sum areas for W waves would not fit in LDS uses fewer waves.
  * Results change with W > 1 by rounding only (see NLCH_ALGO_AUTOTUNE).
+ * R = 4 (other fields 0) selects the tiled one-step kernel (32 x 32 output
+ * tiles with their halo staged in LDS) for the groups and discs it is built
+ * for (FP32 or FP16 arithmetic, m <= 16), with states bit-identical to
+ * R = 1, W = 1; it is also the default for one or a few samples of a lattice,
+ * where the streaming shape would give fewer than 1024 waves.
  * Host only; returns NLCH_EINVAL for values outside those ranges. */
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
 
@@ -358,7 +372,7 @@ int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap);
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *nlch_last_error(void);
 
-/* ABI version: 4 (increments on any change to a struct, constant or function
+/* ABI version: 5 (increments on any change to a struct, constant or function
  * signature declared here). */
 int nlch_version(void);
 

@@ -19,6 +19,25 @@
 // step's z, kept in the workspace (warm start), so a solve split over several
 // calls agrees with one call to the Newton tolerance, not bit for bit.
 //
+// For xi <= 0 the term xi u is concave and is taken at the previous step
+// (convex splitting; with xi > 0 it stays implicit as above):
+//
+//     u + tau A mu = r',   r' = u_old + tau A (g - xi u_old),   mu in N_K(u),
+//
+// a strictly convex problem (u is the projection of r' onto K in the norm of
+// (tau A)^{-1}) with a unique solution.  It is solved by the primal-dual
+// active-set iteration on the complementarity problem in mu, whose matrix
+// tau A is an M-matrix: the active sets A+ = {mu + (u - 1) > 0} and
+// A- = {mu + (u + 1) < 0} fix u = +-1 there and mu = 0 elsewhere; conjugate
+// gradients solve (tau A)_AA mu_A = r'_A - u_A (the rows and columns of the
+// inactive sites removed; warm-started from the previous mu), and the
+// inactive sites take u_I = r'_I - (tau A mu)_I.  The iteration stops when the
+// sets repeat and the residual of the active rows, evaluated afresh in FP64,
+// is below 1e-13 max(1, |r'|).  Within a call each step starts from the
+// previous step's mu; a call's first step from mu = 0, u = r'.  A batch whose
+// samples have both signs of xi launches both kernels; each workgroup of a
+// kernel whose sign is not its sample's returns at once.
+//
 // One workgroup per sample.  k_b2_step keeps every vector in FP64 in a
 // per-sample global workspace.  The on-chip variant k_b2_step_lds keeps the
 // Newton-level vectors (z, r, F, the Newton direction) and the CG residual in
@@ -26,8 +45,8 @@
 // part in LDS, low part in registers); the Newton residual test is FP64 in
 // both.  Every decision is taken on block-reduced scalars, so control
 // flow is uniform across the workgroup; every loop has a fixed cap, and a
-// sample whose Newton iteration has not converged at the cap gets a NaN
-// state (hence a NaN output of interest).
+// sample whose Newton (or active-set) iteration has not converged at the cap
+// gets a NaN state (hence a NaN output of interest).
 #include <algorithm>
 #include <type_traits>
 
@@ -42,6 +61,21 @@ constexpr int kB2Waves = kB2Threads / 64;
 constexpr int kMaxNewton = 40;
 constexpr int kMaxCg = 4000;
 constexpr int kMaxHalvings = 30;
+constexpr int kMaxPdas = 60;
+
+// Active-set code of a site from (u, mu) with c = 1: +1 (A+), -1 (A-), 0.
+__device__ __forceinline__ double pdas_code(double u, double mu) {
+    return mu + (u - 1.0) > 0.0 ? 1.0 : (mu + (u + 1.0) < 0.0 ? -1.0 : 0.0);
+}
+
+// Stopping level of a split-step CG solve in the norm s.M^-1 s (M^-1 = d_act
+// on the active rows): the residual below 1e-14 max(1, |r'|), or, while the
+// active sets still change, reduced 1e4-fold.
+__device__ __forceinline__ double pdas_cg_stop(double rz0, double d_act, double scale,
+                                               bool changed) {
+    const double target = d_act * (1e-14 * scale) * (1e-14 * scale);
+    return changed ? fmax(1e-8 * rz0, target) : target;
+}
 
 __device__ __forceinline__ double clampd(double v) {
     return v < -1.0 ? -1.0 : (v > 1.0 ? 1.0 : v);
@@ -50,6 +84,18 @@ __device__ __forceinline__ double clampd(double v) {
 __device__ __forceinline__ double phi(double s, double xi) {
     const double a = fabs(s);
     return a <= xi ? s * s / (2.0 * xi) : a - 0.5 * xi;
+}
+
+// phi(z + d) - phi(z) - d phi'(z), phi'(z) = clamp(z / xi): the part of the
+// change of phi beyond its linearisation, exact where z and z + d lie in one
+// piece (d^2 / (2 xi) in the quadratic piece, 0 in a linear one), so that the
+// line search's decrease test has no cancellation between large terms.
+__device__ __forceinline__ double phi_rem(double z, double d, double xi) {
+    const double t = z + d;
+    const bool qz = fabs(z) <= xi, qt = fabs(t) <= xi;
+    if (qz && qt) return d * d / (2.0 * xi);
+    if (!qz && !qt && (z > 0.0) == (t > 0.0)) return 0.0;
+    return phi(t, xi) - phi(z, xi) - d * clampd(z / xi);
 }
 
 // (tau A v)_i = tau beta1 v_i - tau beta2 n^2 (v_E + v_W + v_N + v_S - 4 v_i),
@@ -91,7 +137,9 @@ __device__ __forceinline__ double block_sum1(double v, double *red) {
     return a[0];
 }
 
-template <class TS, bool GAUSS>
+// SPLIT: the step for xi <= 0 (active-set iteration); else the step for
+// xi > 0 (Newton).  Workgroups of the other sign return at once.
+template <class TS, bool GAUSS, bool SPLIT>
 __global__ __launch_bounds__(kB2Threads) void k_b2_step(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
@@ -100,6 +148,7 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
     __shared__ double red[kB2Waves * 4];
     const int j = blockIdx.x;
     const SampleDesc d = sd[ids[j]];
+    if ((d.xi > 0.0) == SPLIT) return;
     const int n = geo->n, m = geo->m;
     const int nn = n * n;
     const TS *u = in + d.offset;
@@ -134,7 +183,7 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
                 lsum += wt * (ui - v);
             }
         }
-        Q[i] = gs * acc;
+        Q[i] = SPLIT ? gs * acc - xi * ui : gs * acc;  // g, or g - xi u_old
         e_ul += ui * lsum;
         e_pot += 1.0 - ui * ui;
     }
@@ -147,6 +196,96 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
         }
     }
     __syncthreads();
+    if constexpr (SPLIT) {
+        // r' = u_old + tau A (g - xi u_old); u (U), mu (M, kept between the
+        // steps of a call) and the active-set code of the last iteration (C;
+        // 2 before the first, so that it counts as a change)
+        double *U = Z, *M = F, *C = X;
+        double rr = 0.0;
+        for (int i = tid; i < nn; i += kB2Threads) {
+            const int y = i / n, x = i - y * n;
+            const double r = (double)u[i] + tau_a(Q, i, y, x, n, nn, tb1, tb2n2);
+            R[i] = r;
+            if (!warm) M[i] = 0.0;
+            C[i] = 2.0;
+            rr += r * r;
+        }
+        const double scale = fmax(1.0, sqrt(block_sum1(rr, red)));  // (its barrier: R, M done)
+        for (int i = tid; i < nn; i += kB2Threads) {
+            const int y = i / n, x = i - y * n;
+            U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
+        }
+        __syncthreads();
+        const double d_act = 1.0 / (tb1 + 4.0 * tb2n2);  // Jacobi: one value on the active rows
+        bool ok = false;
+        for (int it = 0;; ++it) {
+            // active sets from (u, mu); u = +-1 on them, mu = 0 off them
+            double cs[2] = {0.0, 0.0};  // changed sites, |s|^2
+            for (int i = tid; i < nn; i += kB2Threads) {
+                const double c = pdas_code(U[i], M[i]);
+                if (c != C[i]) cs[0] += 1.0;
+                C[i] = c;
+                if (c != 0.0)
+                    U[i] = c;
+                else
+                    M[i] = 0.0;
+            }
+            __syncthreads();
+            // residual of the active rows, s = r'_A - u_A - (tau A mu)_A
+            for (int i = tid; i < nn; i += kB2Threads) {
+                const int y = i / n, x = i - y * n;
+                const double sv =
+                    C[i] != 0.0 ? R[i] - U[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : 0.0;
+                S[i] = sv;
+                P[i] = sv * d_act;
+                cs[1] += sv * sv;
+            }
+            block_sums<2>(cs, red);
+            if (cs[0] == 0.0 && sqrt(cs[1]) <= 1e-13 * scale) {
+                ok = true;
+                break;
+            }
+            if (it == kMaxPdas) break;
+            // CG on (tau A)_AA from the current mu (directions vanish on the
+            // inactive sites)
+            double rz = cs[1] * d_act;
+            const double stop = pdas_cg_stop(rz, d_act, scale, cs[0] != 0.0);
+            for (int k = 0; k < kMaxCg && rz > stop; ++k) {
+                double pq = 0.0;
+                for (int i = tid; i < nn; i += kB2Threads) {
+                    const int y = i / n, x = i - y * n;
+                    const double q = C[i] != 0.0 ? tau_a(P, i, y, x, n, nn, tb1, tb2n2) : 0.0;
+                    Q[i] = q;
+                    pq += P[i] * q;
+                }
+                pq = block_sum1(pq, red);
+                if (!(pq > 0.0)) break;
+                const double alpha = rz / pq;
+                double rn = 0.0;
+                for (int i = tid; i < nn; i += kB2Threads) {
+                    M[i] += alpha * P[i];
+                    const double sv = S[i] - alpha * Q[i];
+                    S[i] = sv;
+                    rn += sv * (sv * d_act);
+                }
+                rn = block_sum1(rn, red);
+                const double beta = rn / rz;
+                rz = rn;
+                for (int i = tid; i < nn; i += kB2Threads) P[i] = S[i] * d_act + beta * P[i];
+                __syncthreads();
+            }
+            __syncthreads();
+            // u on the inactive sites
+            for (int i = tid; i < nn; i += kB2Threads) {
+                const int y = i / n, x = i - y * n;
+                if (C[i] == 0.0) U[i] = R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2);
+            }
+            __syncthreads();
+        }
+        const double nan = __builtin_nan("");
+        for (int i = tid; i < nn; i += kB2Threads) uo[i] = to_store<TS>(ok ? U[i] : nan);
+        return;
+    }
     // r = u_old + tau A g; Newton starts from z = xi u_old, or (warm) from
     // the previous step's z, which the workspace still holds
     double rr = 0.0;
@@ -216,26 +355,23 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
                 P[i] = S[i] * (fabs(Z[i]) < xi ? d_ina : d_act) + beta * P[i];
             __syncthreads();
         }
-        // Armijo backtracking on Phi along x:
-        // Phi(z + a x) - Phi(z) = a s1 + a^2/2 s2 + sum(phi(z + a x) - phi(z)) - a s3
-        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        // Armijo backtracking on Phi along x, with the change written as
+        // Phi(z + a x) - Phi(z) = a F.x + a^2/2 x.tau A x
+        //                         + sum(phi(z + a x) - phi(z) - a x phi'(z))
+        // (every term of the size of the decrease, none cancelling)
+        double sm[2] = {0.0, 0.0};  // x.tau A x, F.x
         for (int i = tid; i < nn; i += kB2Threads) {
             const int y = i / n, x = i - y * n;
-            const double taz = F[i] - clampd(Z[i] / xi) + R[i];
-            const double tax = tau_a(X, i, y, x, n, nn, tb1, tb2n2);
-            sm[0] += X[i] * taz;
-            sm[1] += X[i] * tax;
-            sm[2] += R[i] * X[i];
-            sm[3] += F[i] * X[i];
+            sm[0] += X[i] * tau_a(X, i, y, x, n, nn, tb1, tb2n2);
+            sm[1] += F[i] * X[i];
         }
-        block_sums<4>(sm, red);
+        block_sums<2>(sm, red);
         double a = 1.0;
         for (int h = 0; h < kMaxHalvings; ++h) {
-            double dp = 0.0;
-            for (int i = tid; i < nn; i += kB2Threads)
-                dp += phi(Z[i] + a * X[i], xi) - phi(Z[i], xi);
-            dp = block_sum1(dp, red);
-            if (a * sm[0] + 0.5 * a * a * sm[1] + dp - a * sm[2] <= 1e-4 * a * sm[3]) break;
+            double rem = 0.0;
+            for (int i = tid; i < nn; i += kB2Threads) rem += phi_rem(Z[i], a * X[i], xi);
+            rem = block_sum1(rem, red);
+            if (a * sm[1] + 0.5 * a * a * sm[0] + rem <= 1e-4 * a * sm[1]) break;
             a *= 0.5;
         }
         for (int i = tid; i < nn; i += kB2Threads) Z[i] += a * X[i];
@@ -336,7 +472,7 @@ __device__ __forceinline__ double sum1_lds(double v, double *red) {
     return a[0];
 }
 
-template <class TS, bool GAUSS, int NN, int THREADS = b2_lds_threads(NN * NN)>
+template <class TS, bool GAUSS, bool SPLIT, int NN, int THREADS = b2_lds_threads(NN * NN)>
 __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, const double *__restrict__ ewd,
@@ -351,6 +487,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
     auto red = [&]() { rsel ^= 1; return red2[rsel]; };
     const int j = blockIdx.x;
     const SampleDesc d = sd[ids[j]];
+    if ((d.xi > 0.0) == SPLIT) return;
     // the lattice size is a compile-time constant, so that the stencil's
     // LDS offsets are instruction immediates rather than registers
     constexpr int n = NN;
@@ -432,7 +569,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
                     }
                 }
             }
-            G[i] = gs * acc;
+            G[i] = SPLIT ? gs * acc - xi * ui : gs * acc;  // g, or g - xi u_old
             if (EN_) {
                 e_ul += ui * lsum;
                 e_pot += 1.0 - ui * ui;
@@ -458,7 +595,12 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         const double ui = (double)u[i];
         const double r = ui + tau_a(G, i, y, x, n, nn, tb1, tb2n2);
         R[i] = r;
-        if (!warm) Z[i] = xi * ui;  // else z of the previous step, in place
+        if constexpr (SPLIT) {
+            if (!warm) F[i] = 0.0;  // mu; else the previous step's, in place
+            X[i] = 2.0;             // active-set code (2: none yet)
+        } else {
+            if (!warm) Z[i] = xi * ui;  // else z of the previous step, in place
+        }
         rr += r * r;
     }
     const double scale = fmax(1.0, sqrt(sum1_lds<kB2LdsWaves>(rr, red())));
@@ -492,56 +634,17 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         if (y == n - 1) Pl[q - n * W] = v;
     };
 
-    // inverse diagonal of J (Jacobi preconditioner): active and inactive sites
+    // inverse diagonal of the CG operator (Jacobi preconditioner): active
+    // and inactive sites (the split step's inactive rows are removed)
     const double d_act = uniform_f64(1.0 / (tb1 + 4.0 * tb2n2)),
-                 d_ina = uniform_f64(1.0 / (tb1 + 4.0 * tb2n2 + 1.0 / xi));
-    bool ok = false;
-    for (int it = 0;; ++it) {
-        // F(z), the CG start (direction -M^-1 F, to LDS) and the inactive-set mask
-        double f2r[2] = {0.0, 0.0};  // |F|^2 and F.M^-1 F
-        unsigned mask = 0;  // bit k: site t + THREADS k inactive (|z| < xi)
-#pragma unroll 1
-        for (int k = 0; k < SPT; ++k) {
-            const int i = site(k);
-            if (valid(k)) {
-                const int y = i / n, x = i - y * n;
-                const double zi = Z[i];
-                const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(zi / xi) - R[i];
-                const bool ina = fabs(zi) < xi;
-                const double dv = ina ? d_ina : d_act;
-                F[i] = f;
-                put(k, -f * dv);
-                if (ina) mask |= 1u << k;
-                f2r[0] += f * f;
-                f2r[1] += f * (f * dv);
-            }
-        }
-        block_sums_lds<2, kB2LdsWaves>(f2r, red());  // also makes Pl visible
-        const double f2 = f2r[0];
-        if (sqrt(f2) <= 1e-13 * scale) {
-            ok = true;
-            break;
-        }
-        if (it == kMaxNewton) break;
-        // The CG residual in FP64 (registers); the solution as an FP32 pair
-        // (a plain FP32 solution limits how much each inexact Newton step
-        // gains, which costs extra Newton steps).  The CG direction is kept
-        // in FP32: the solution and the residual are updated with the same
-        // rounded direction and its FP64 operator product, so they stay
-        // consistent and the residual reaches FP64 tolerances; the rounding
-        // only perturbs the conjugacy of the directions.
-        const double inv_xi = uniform_f64(1.0 / xi);
-        double Sr[SPT];
-        float Xlo[SPT];  // the solution is Xl + Xlo (an FP32 pair, ~48 bits)
-#pragma unroll
-        for (int k = 0; k < SPT; ++k) {
-            Sr[k] = valid(k) ? -F[site(k)] : 0.0;
-            if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
-            Xlo[k] = 0.0f;
-        }
-        const double eta = fmin(1e-2, sqrt(f2) / scale);
-        const double stop = eta * eta * f2r[1];
-        double rz = f2r[1];
+                 d_ina = SPLIT ? 0.0 : uniform_f64(1.0 / (tb1 + 4.0 * tb2n2 + 1.0 / xi));
+    const double inv_xi = SPLIT ? 0.0 : uniform_f64(1.0 / xi);
+    // Conjugate gradients from the solution 0 (Xl + Xlo, zeroed by the
+    // caller) with residual Sr and first direction M^-1 Sr already in Pl, on
+    // tau A + diag(1/xi on the inactive sites) (Newton), or on tau A with the
+    // rows and columns of the inactive sites removed (SPLIT: the residual and
+    // the direction vanish there and stay zero).
+    auto cg = [&](unsigned mask, double(&Sr)[SPT], float(&Xlo)[SPT], double rz, double stop) {
         for (int kk = 0; kk < kMaxCg && rz > stop; ++kk) {
             // the per-site selections of the preconditioner are made in
             // every iteration: an empty asm statement hides the two values
@@ -571,6 +674,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
                 const double pi = v.c;
                 const double ap = tb1 * pi - tb2n2 * ((double)v.e + (double)v.w + (double)v.n +
                                                       (double)v.s - 4.0 * pi);
+                if constexpr (SPLIT) return (mask >> k) & 1u ? 0.0 : ap;
                 return ap + ((mask >> k) & 1u ? pi * inv_xi : 0.0);
             };
             double pq = 0.0;
@@ -620,28 +724,149 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
             }
             __syncthreads();
         }
+    };
+
+    bool ok = false;
+    if constexpr (SPLIT) {
+        // u (U), mu (M; kept between the steps of a call) and the active-set
+        // code of the last iteration (C) in the workspace; each CG solve
+        // accumulates the change of mu in Xl + Xlo
+        double *U = Z, *M = F, *C = X;
+        for (int i = tid; i < nn; i += kB2LdsThreads) {
+            const int y = i / n, x = i - y * n;
+            U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
+        }
+        __syncthreads();
+        for (int it = 0;; ++it) {
+            // active sets from (u, mu); u = +-1 on them, mu = 0 off them
+            double cs[2] = {0.0, 0.0};  // changed sites, |s|^2
+            unsigned mask = 0;          // bit k: site t + THREADS k inactive
+#pragma unroll 1
+            for (int k = 0; k < SPT; ++k) {
+                const int i = site(k);
+                if (valid(k)) {
+                    const double c = pdas_code(U[i], M[i]);
+                    if (c != C[i]) cs[0] += 1.0;
+                    C[i] = c;
+                    if (c != 0.0) {
+                        U[i] = c;
+                    } else {
+                        M[i] = 0.0;
+                        mask |= 1u << k;
+                    }
+                }
+            }
+            __syncthreads();
+            // residual of the active rows, s = r'_A - u_A - (tau A mu)_A, in
+            // FP64 from mu (to G, whose g is no longer needed); the CG start
+#pragma unroll 1
+            for (int k = 0; k < SPT; ++k) {
+                const int i = site(k);
+                if (valid(k)) {
+                    const int y = i / n, x = i - y * n;
+                    const double sv = (mask >> k) & 1u
+                                          ? 0.0
+                                          : R[i] - U[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2);
+                    G[i] = sv;
+                    put(k, sv * d_act);
+                    cs[1] += sv * sv;
+                }
+            }
+            double Sr[SPT];
+            float Xlo[SPT];
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                Sr[k] = valid(k) ? G[site(k)] : 0.0;
+                if (valid(k)) Xl[site(k)] = 0.0f;
+                Xlo[k] = 0.0f;
+            }
+            block_sums_lds<2, kB2LdsWaves>(cs, red());  // also makes Pl visible
+            if (cs[0] == 0.0 && sqrt(cs[1]) <= 1e-13 * scale) {
+                ok = true;
+                break;
+            }
+            if (it == kMaxPdas) break;
+            const double rz = cs[1] * d_act;
+            cg(mask, Sr, Xlo, rz, pdas_cg_stop(rz, d_act, scale, cs[0] != 0.0));
+#pragma unroll
+            for (int k = 0; k < SPT; ++k)
+                if (valid(k)) M[site(k)] += (double)Xl[site(k)] + (double)Xlo[k];
+            __syncthreads();
+            // u on the inactive sites
+            for (int i = tid; i < nn; i += kB2LdsThreads) {
+                const int y = i / n, x = i - y * n;
+                if (C[i] == 0.0) U[i] = R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2);
+            }
+            __syncthreads();
+        }
+        const double nan = __builtin_nan("");
+        for (int i = tid; i < nn; i += kB2LdsThreads) uo[i] = to_store<TS>(ok ? U[i] : nan);
+        return;
+    }
+    for (int it = 0;; ++it) {
+        // F(z), the CG start (direction -M^-1 F, to LDS) and the inactive-set mask
+        double f2r[2] = {0.0, 0.0};  // |F|^2 and F.M^-1 F
+        unsigned mask = 0;  // bit k: site t + THREADS k inactive (|z| < xi)
+#pragma unroll 1
+        for (int k = 0; k < SPT; ++k) {
+            const int i = site(k);
+            if (valid(k)) {
+                const int y = i / n, x = i - y * n;
+                const double zi = Z[i];
+                const double f = tau_a(Z, i, y, x, n, nn, tb1, tb2n2) + clampd(zi / xi) - R[i];
+                const bool ina = fabs(zi) < xi;
+                const double dv = ina ? d_ina : d_act;
+                F[i] = f;
+                put(k, -f * dv);
+                if (ina) mask |= 1u << k;
+                f2r[0] += f * f;
+                f2r[1] += f * (f * dv);
+            }
+        }
+        block_sums_lds<2, kB2LdsWaves>(f2r, red());  // also makes Pl visible
+        const double f2 = f2r[0];
+        if (sqrt(f2) <= 1e-13 * scale) {
+            ok = true;
+            break;
+        }
+        if (it == kMaxNewton) break;
+        // The CG residual in FP64 (registers); the solution as an FP32 pair
+        // (a plain FP32 solution limits how much each inexact Newton step
+        // gains, which costs extra Newton steps).  The CG direction is kept
+        // in FP32: the solution and the residual are updated with the same
+        // rounded direction and its FP64 operator product, so they stay
+        // consistent and the residual reaches FP64 tolerances; the rounding
+        // only perturbs the conjugacy of the directions.
+        double Sr[SPT];
+        float Xlo[SPT];  // the solution is Xl + Xlo (an FP32 pair, ~48 bits)
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            Sr[k] = valid(k) ? -F[site(k)] : 0.0;
+            if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
+            Xlo[k] = 0.0f;
+        }
+        const double eta = fmin(1e-2, sqrt(f2) / scale);
+        const double stop = eta * eta * f2r[1];
+        double rz = f2r[1];
+        cg(mask, Sr, Xlo, rz, stop);
 #pragma unroll
         for (int k = 0; k < SPT; ++k)
             if (valid(k)) X[site(k)] = (double)Xl[site(k)] + (double)Xlo[k];
         __syncthreads();
-        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        // Armijo backtracking as in k_b2_step
+        double sm[2] = {0.0, 0.0};  // x.tau A x, F.x
         for (int i = tid; i < nn; i += kB2LdsThreads) {
             const int y = i / n, x = i - y * n;
-            const double taz = F[i] - clampd(Z[i] / xi) + R[i];
-            const double tax = tau_a(X, i, y, x, n, nn, tb1, tb2n2);
-            sm[0] += X[i] * taz;
-            sm[1] += X[i] * tax;
-            sm[2] += R[i] * X[i];
-            sm[3] += F[i] * X[i];
+            sm[0] += X[i] * tau_a(X, i, y, x, n, nn, tb1, tb2n2);
+            sm[1] += F[i] * X[i];
         }
-        block_sums_lds<4, kB2LdsWaves>(sm, red());
+        block_sums_lds<2, kB2LdsWaves>(sm, red());
         double a = 1.0;
         for (int h = 0; h < kMaxHalvings; ++h) {
-            double dp = 0.0;
-            for (int i = tid; i < nn; i += kB2LdsThreads)
-                dp += phi(Z[i] + a * X[i], xi) - phi(Z[i], xi);
-            dp = sum1_lds<kB2LdsWaves>(dp, red());
-            if (a * sm[0] + 0.5 * a * a * sm[1] + dp - a * sm[2] <= 1e-4 * a * sm[3]) break;
+            double rem = 0.0;
+            for (int i = tid; i < nn; i += kB2LdsThreads) rem += phi_rem(Z[i], a * X[i], xi);
+            rem = sum1_lds<kB2LdsWaves>(rem, red());
+            if (a * sm[1] + 0.5 * a * a * sm[0] + rem <= 1e-4 * a * sm[1]) break;
             a *= 0.5;
         }
         for (int i = tid; i < nn; i += kB2LdsThreads) Z[i] += a * X[i];
@@ -652,7 +877,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         uo[i] = to_store<TS>(ok ? clampd(Z[i] / xi) : nan);
 }
 
-template <class TS>
+template <class TS, bool SPLIT>
 hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, double *epart,
                     bool warm) {
     // on-chip variant for the lattices of the multifidelity study
@@ -677,25 +902,38 @@ hipError_t b2_typed(const Group &g, const void *in, void *out, hipStream_t s, do
     const bool gauss = g.kernel == 1;
     switch (g.n) {
         case 64:
-            return gauss ? lds_launch(k_b2_step_lds<TS, true, 64>, 64)
-                         : lds_launch(k_b2_step_lds<TS, false, 64>, 64);
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, SPLIT, 64>, 64)
+                         : lds_launch(k_b2_step_lds<TS, false, SPLIT, 64>, 64);
         case 88:
-            return gauss ? lds_launch(k_b2_step_lds<TS, true, 88>, 88)
-                         : lds_launch(k_b2_step_lds<TS, false, 88>, 88);
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, SPLIT, 88>, 88)
+                         : lds_launch(k_b2_step_lds<TS, false, SPLIT, 88>, 88);
         case 128:
-            return gauss ? lds_launch(k_b2_step_lds<TS, true, 128>, 128)
-                         : lds_launch(k_b2_step_lds<TS, false, 128>, 128);
+            return gauss ? lds_launch(k_b2_step_lds<TS, true, SPLIT, 128>, 128)
+                         : lds_launch(k_b2_step_lds<TS, false, SPLIT, 128>, 128);
         default:
             break;
     }
     dim3 grid((unsigned)g.nids), block(kB2Threads);
     if (g.kernel == 1)
-        hipLaunchKernelGGL((k_b2_step<TS, true>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
-                           (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
+        hipLaunchKernelGGL((k_b2_step<TS, true, SPLIT>), grid, block, 0, s, g.sd, g.ids, g.geo,
+                           g.ewd, (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
     else
-        hipLaunchKernelGGL((k_b2_step<TS, false>), grid, block, 0, s, g.sd, g.ids, g.geo, g.ewd,
-                           (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
+        hipLaunchKernelGGL((k_b2_step<TS, false, SPLIT>), grid, block, 0, s, g.sd, g.ids, g.geo,
+                           g.ewd, (const TS *)in, (TS *)out, g.ws, epart, (int)warm);
     return hipGetLastError();
+}
+
+// The Newton kernel for the group's samples with xi > 0, then the split-step
+// kernel for those with xi <= 0 (each launched only if it has samples).
+template <class TS>
+hipError_t b2_both(const Group &g, const void *in, void *out, hipStream_t s, double *epart,
+                   bool warm) {
+    if (g.b2_newton > 0) {
+        const hipError_t e = b2_typed<TS, false>(g, in, out, s, epart, warm);
+        if (e != hipSuccess) return e;
+    }
+    if (g.b2_split > 0) return b2_typed<TS, true>(g, in, out, s, epart, warm);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -704,9 +942,9 @@ hipError_t launch_b2_step(int prec, const Group &g, const void *in, void *out, h
                           double *epart, bool warm) {
     if (!g.ws || g.n > kB2MaxN || g.lo != 0) return hipErrorInvalidValue;
     switch (prec) {
-        case kF64: return b2_typed<double>(g, in, out, s, epart, warm);
-        case kF32: return b2_typed<float>(g, in, out, s, epart, warm);
-        default: return b2_typed<half_t>(g, in, out, s, epart, warm);
+        case kF64: return b2_both<double>(g, in, out, s, epart, warm);
+        case kF32: return b2_both<float>(g, in, out, s, epart, warm);
+        default: return b2_both<half_t>(g, in, out, s, epart, warm);
     }
 }
 

@@ -194,11 +194,17 @@ int nlch::sample_coef(const nlch_model &md, const ModelInfo &mi, double c_F, dou
     c.xi_h = c.c_gamma_h - c_F;
     const double tb = md.tau * md.beta1;
     const double den = 1.0 + tb * c.xi_h;
+    // beta2 > 0: a strictly convex step for either sign of xi_h (the Newton
+    // step for xi_h > 0, the split step for xi_h <= 0), which does not use
+    // c1, a and b; they are 0 where 1 + tau beta1 xi_h <= 0
+    if (md.beta2 > 0.0 && !(den > 0.0)) {
+        if (!std::isfinite(c.xi_h))
+            return fail(NLCH_EINVAL, "%s: xi_h = %g is not finite", what, c.xi_h);
+        c.c1 = c.a = c.b = 0.0;
+        return NLCH_OK;
+    }
     if (!(den > 0.0))
         return fail(NLCH_EINVAL, "%s: 1 + tau*beta1*xi_h = %g must be > 0", what, den);
-    if (md.beta2 > 0.0 && !(c.xi_h > 0.0))
-        return fail(NLCH_EUNSUPPORTED, "%s: beta2 > 0 needs xi_h = c_gamma_h - c_F > 0 (the "
-                    "step is then a strictly convex problem); xi_h = %g", what, c.xi_h);
     c.c1 = tb / den;
     c.a = c.c1 * c_F;
     c.b = c.c1 * h2 * amp;
@@ -468,6 +474,12 @@ int get_batch(const nlch_model *models, int32_t n_models, const std::vector<Mode
         int rc = choose_variant(base, prec, acc64, mi[i], models[i], is_batch, &variant);
         if (rc) return rc;
         Group g = make_group(models[i], mi[i], i, (int)per_model[i].size(), prec);
+        for (int32_t id : per_model[i]) {
+            if (sd[(size_t)id].xi > 0.0)
+                ++g.b2_newton;
+            else
+                ++g.b2_split;
+        }
         id_off.push_back(ids.size());
         ids.insert(ids.end(), per_model[i].begin(), per_model[i].end());
         b->groups.push_back(g);
@@ -952,7 +964,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
 
 extern "C" {
 
-int nlch_version(void) { return 4; }
+int nlch_version(void) { return 5; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 

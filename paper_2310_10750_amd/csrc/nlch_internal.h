@@ -75,6 +75,8 @@ struct Group {
     int32_t res_cols;        // resident kernel: columns per lane and rows each
     int32_t res_rows;        //   lane walks (0 = default)
     int32_t tile;            // row-run steps on 32 x 32 output tiles (k_tile)
+    int32_t b2_newton;       // beta2 > 0 groups: samples with xi_h > 0 (Newton step)
+    int32_t b2_split;        //   and with xi_h <= 0 (split step)
 };
 
 // Heuristic streaming shape of the row-run kernel: lanes own R columns of a

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
             "nlch_version"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert nlch.nlch_version() == 4
+    assert nlch.nlch_version() == 5
 
 
 def test_struct_layouts_match_header():
@@ -104,8 +104,8 @@ def test_model_validation_errors():
             setattr(md, k, v)
         assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EINVAL, kw
     md = _good_model()
-    md.beta2 = 0.05
-    assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EUNSUPPORTED
+    md.beta2 = 0.05  # xi_h < 0: the split step, accepted
+    assert nlch.nlch_model_constants(md)[1] < 0
     md = _good_model()
     md.n, md.delta = 256, 60 / 256
     assert _err(nlch.nlch_model_constants, md) == nlch.NLCH_EUNSUPPORTED
@@ -122,7 +122,8 @@ def test_step_argument_errors():
     assert _err(nlch.nlch_step, md, 1, 0, 4096, 4096 + 100) == E     # overlap
     assert _err(nlch.nlch_step, md, 1, 0, None, 8192) == E
     md.beta2 = 0.1
-    assert _err(nlch.nlch_step, md, 1, 0, 4096, 1 << 20) == nlch.NLCH_EUNSUPPORTED
+    md.n, md.delta = 512, 3 / 512  # beta2 > 0 is built for n <= 256
+    assert _err(nlch.nlch_step, md, 1, 0, 4096, 1 << 22) == nlch.NLCH_EUNSUPPORTED
 
 
 def test_solve_batch_argument_errors():
@@ -176,15 +177,21 @@ def test_mfmc_argument_errors():
 
 
 def test_beta2_validation():
-    """beta2 > 0 is accepted for xi_h > 0 and n <= 256, rejected (before any
-    device work) for a non-convex step, a larger lattice or RESIDENT."""
+    """beta2 > 0 is accepted for either sign of xi_h and n <= 256 (also where
+    1 + tau beta1 xi_h <= 0, which only the beta2 = 0 step divides by), and
+    rejected (before any device work) for a larger lattice or RESIDENT."""
     amp, sigma, _ = synth.gaussian_params(0.25)
     ok = nlch.make_model(32, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01)
     c, xi, c1 = nlch.nlch_model_constants(ok)
     assert xi > 0
     nc = nlch.make_model(32, 0.125, 1, amp, sigma, beta2=0.05, tau=0.01)
-    assert _err(nlch.nlch_model_constants, nc) == nlch.NLCH_EUNSUPPORTED
-    assert "xi_h" in nlch.nlch_last_error()
+    c, xi, c1 = nlch.nlch_model_constants(nc)
+    assert xi < 0 and c1 > 0
+    steep = nlch.make_model(32, 0.125, 1, amp, sigma, beta2=0.05, tau=50.0)
+    c, xi, c1 = nlch.nlch_model_constants(steep)  # 1 + tau beta1 xi_h < 0
+    assert 1 + 50.0 * xi < 0 and c1 == 0
+    steep.beta2 = 0.0
+    assert _err(nlch.nlch_model_constants, steep) == nlch.NLCH_EINVAL
     big = nlch.make_model(512, 0.25, 1, amp, sigma, beta2=0.05, tau=0.01)
     assert _err(nlch.nlch_model_constants, big) == nlch.NLCH_EUNSUPPORTED
     neg = nlch.make_model(32, 0.25, 1, amp, sigma, beta2=-0.05, tau=0.01)
@@ -194,10 +201,6 @@ def test_beta2_validation():
     assert _err(nlch.nlch_solve_batch, [ok], S, 5, 1, nlch.NLCH_ALGO_RESIDENT, b, 2 * b,
                 3 * b) == nlch.NLCH_EUNSUPPORTED
     assert _err(nlch.nlch_solve_batch, [ok], S, 5, 1, 0, b, None, 3 * b) == nlch.NLCH_EINVAL
-    # a sample whose own c_F makes xi_h <= 0
-    S2 = [nlch.nlch_sample(0, 0, 1.5, amp, 0)]
-    assert _err(nlch.nlch_solve_batch, [ok], S2, 5, 1, 0, b, 2 * b,
-                3 * b) == nlch.NLCH_EUNSUPPORTED
 
 
 def test_volume_constraint_validation(orc):

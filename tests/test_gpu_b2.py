@@ -1,9 +1,11 @@
 """GPU parity of the beta2 > 0 step (eq. nonl_CH_nm with beta1, beta2 > 0)
 against the FP64 oracle (oracle.b2), through the C ABI.
 
-Both sides solve the same strictly convex step (xi_h > 0) to a residual of
-~1e-13 relative, so FP64 states agree to 1e-10; FP32 and FP16 storage add the
-rounding of the stored state (bars 1e-6 and 1e-3, as for beta2 = 0)."""
+Both sides solve the same strictly convex step -- the Newton step for
+xi_h > 0, the split step (xi_h u at the previous step) for xi_h <= 0 -- to a
+residual of ~1e-13 relative, so FP64 states agree to 1e-10; FP32 and FP16
+storage add the rounding of the stored state (bars 1e-6 and 1e-3, as for
+beta2 = 0)."""
 import math
 
 import numpy as np
@@ -130,18 +132,162 @@ def test_b2_mixed_batch_and_resume(orc):
     assert abs(a.ooi_host()[1, 1] - f1) <= 1e-12 * f1
 
 
-def test_b2_rejects_nonconvex_steps():
-    amp, sigma, _ = synth.gaussian_params(0.25)
-    # delta < delta_hf truncates the kernel: xi_h < 0
-    w = synth.Workload("nc", [synth.Model(32, 0.125, 1, amp, sigma, beta2=0.05, tau=0.01)],
-                       [synth.Sample(0, 1.0, amp, "iid", 1, 0)], 3, "f64")
-    b = DeviceBatch(w)
-    before = b.state.clone()
-    with pytest.raises(nlch.NlchError) as e:
-        b.solve()
-    assert e.value.code == nlch.NLCH_EUNSUPPORTED
+SPLIT_CASES = [(16, 4, 0, -0.05), (24, 9, 1, -0.2), (40, 16, 1, -0.085), (50, 25, 0, -1e-3),
+               (96, 64, 1, -0.085),
+               # lattices with the on-chip (LDS) variant
+               (64, 16, 1, -0.085), (88, 121, 1, -0.04), (128, 256, 1, -0.085),
+               (64, 9, 0, -0.6)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("n,R2,kind,xi", SPLIT_CASES)
+def test_b2_split_one_step(orc, n, R2, kind, xi, prec):
+    """xi_h < 0: one split step at every site against the oracle's
+    active-set solve, with the KKT conditions of mu (FP64)."""
+    print("b2 split one-step n=%d R2=%d kernel=%d xi=%g %s" % (n, R2, kind, xi, prec),
+          flush=True)
+    delta = math.sqrt(R2) / n
+    sigma = delta / 3
+    amp = _amp_for(orc, n, delta, kind, sigma, xi)
+    md = nlch.make_model(n, delta, kind, amp, sigma, c_F=1.0, beta1=1.0, beta2=0.05, tau=0.01)
+    assert nlch.nlch_model_constants(md)[1] < 0
+    u = _rand(n, 11 + n, prec)
+    x = torch.from_numpy(u.reshape(-1)).to(TDT[prec]).to(DEV)
+    y = torch.empty_like(x)
+    ooi = torch.zeros(2, dtype=torch.float64, device=DEV)
+    nlch.nlch_step(md, nlch.PRECISIONS[prec], nlch.NLCH_ALGO_AUTO, x, y, ooi)
     torch.cuda.synchronize()
-    assert torch.equal(before, b.state)
+    got = y.double().cpu().numpy().reshape(n, n)
+    ref, _, _ = b2.step_b2_split(u, n, delta, kind, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+    assert np.max(np.abs(got - ref)) <= TOL[prec]
+    assert np.all(np.abs(got) <= 1)
+    assert abs(ooi.cpu().numpy()[1] - 0.5 * (1 + got.mean())) <= 1e-12
+    if prec == "f64":
+        mu = b2.multiplier(got, u, n, delta, kind, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+        inner = np.abs(got) < 1
+        assert np.max(np.abs(mu[inner])) <= 1e-7
+        assert np.min(mu[got == 1], initial=0.0) >= -1e-7
+        assert np.max(mu[got == -1], initial=0.0) <= 1e-7
+        assert np.any(inner) and np.any(np.abs(got) == 1)  # both sets in use
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_b2_split_trajectory_paper_parameters(orc, prec):
+    """20 steps of the paper's delta = 0.125 model (kernel truncated at half
+    of delta_hf = 0.25: xi_h ~ -0.085) on 32^2: states and OoI against the
+    oracle's trajectory of split steps, and the energy trace."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    m = synth.Model(32, 0.125, 1, amp, sigma, c_F=1.0, beta1=1.0, beta2=0.05, tau=0.01)
+    smp = [synth.Sample(0, 1.0, amp, "nuclei", 6, s, synth.draw_theta(synth.rng_for(6, s)))
+           for s in range(2)]
+    w = synth.Workload("b2split", [m], smp, 20, prec)
+    assert orc.constants(32, 0.125, 1, amp, sigma, 1.0)[1] < -0.05
+    b = DeviceBatch(w, prec)
+    e = b.solve_energy(nlch.NLCH_ALGO_AUTO)
+    torch.cuda.synchronize()
+    E = e.cpu().numpy()
+    o = b.ooi_host()
+    for i, s in enumerate(w.samples):
+        u0 = rounded_initial(w, s, prec)
+        ref, mean, f1 = b2.solve_b2(u0, w.nsteps, m.n, m.delta, m.kernel, s.amp, m.sigma,
+                                    s.c_F, m.beta1, m.beta2, m.tau)
+        rel = 1e-10 if prec == "f64" else 1e-6
+        assert abs(o[i, 1] - f1) <= rel * abs(f1), (i, o[i, 1], f1)
+        assert np.max(np.abs(b.sample_state(i) - ref)) <= (1e-8 if prec == "f64" else 1e-4)
+        e0 = orc.energy(np.clip(u0, -1, 1), m.n, m.delta, m.kernel, s.amp, m.sigma, s.c_F)
+        eK = orc.energy(b.sample_state(i), m.n, m.delta, m.kernel, s.amp, m.sigma, s.c_F)
+        assert abs(E[0, i] - e0) <= 1e-11 * abs(e0)
+        assert abs(E[-1, i] - eK) <= 1e-11 * abs(eK)
+
+
+@pytest.mark.parametrize("n", [40, 64])
+def test_b2_mixed_signs_in_one_group(orc, n):
+    """One model, per-sample c_F on both sides of c_gamma_h: the Newton and
+    the split kernels each take their samples; every sample equals its own
+    single-sample solve bit for bit, a solve split over two calls equals one
+    call to the solver tolerance, and each sample follows the oracle."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    delta = 8.0 / n
+    m = synth.Model(n, delta, 1, amp, sigma, beta2=0.05, tau=0.01)
+    cg = orc.constants(n, delta, 1, amp, sigma, 1.0)[0]
+    cfs = [cg - 0.02, cg + 0.05, cg - 0.0253, cg + 0.2]  # xi_h = 0.02, -0.05, ...
+    smp = [synth.Sample(0, c, amp, "nuclei", 6, k, synth.draw_theta(synth.rng_for(6, k)))
+           for k, c in enumerate(cfs)]
+    w = synth.Workload("mixed_signs", [m], smp, 8, "f64")
+    a = DeviceBatch(w)
+    a.solve()
+    c = DeviceBatch(w)
+    c.solve(nsteps=3)
+    c.solve(nsteps=5)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert np.all(np.isfinite(a.sample_state(k))), ("one call", k)
+        assert np.all(np.isfinite(c.sample_state(k))), ("two calls", k)
+    assert torch.max(torch.abs(a.state - c.state)).item() <= 1e-11
+    for k in range(4):
+        wk = synth.Workload("one", [m], [smp[k]], 8, "f64")
+        bk = DeviceBatch(wk)
+        bk.solve()
+        torch.cuda.synchronize()
+        assert np.array_equal(bk.sample_state(0), a.sample_state(k))
+        u0 = rounded_initial(w, smp[k], "f64")
+        ref, _, _ = b2.solve_b2(u0, 8, n, delta, 1, amp, sigma, cfs[k], 1.0, 0.05, 0.01)
+        assert np.max(np.abs(a.sample_state(k) - ref)) <= 1e-9, k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [64, 128, 40])
+def test_b2_split_extremes(orc, n, prec):
+    """xi_h < 0: u = +-1 (every site active; mu = c_F solves tau A mu =
+    tau beta1 c_F exactly) and u = 0 are stationary; a small cosine mode
+    (every site inactive) takes the linear step u = r'."""
+    print("b2 split extremes n=%d %s" % (n, prec), flush=True)
+    delta = 8.0 / n if n >= 64 else 4.0 / n
+    sigma = delta / 3
+    amp = _amp_for(orc, n, delta, 1, sigma, -0.085)
+    md = nlch.make_model(n, delta, 1, amp, sigma, c_F=1.0, beta1=1.0, beta2=0.05, tau=0.01)
+
+    def step(u):
+        x = torch.from_numpy(u.reshape(-1)).to(TDT[prec]).to(DEV)
+        y = torch.empty_like(x)
+        nlch.nlch_step(md, nlch.PRECISIONS[prec], nlch.NLCH_ALGO_AUTO, x, y, None)
+        torch.cuda.synchronize()
+        return y.double().cpu().numpy().reshape(n, n)
+
+    for c in (1.0, -1.0, 0.0):
+        assert np.all(step(np.full((n, n), c)) == c), c
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    u = 1e-3 * np.cos(2 * np.pi * (3 * xx + 2 * yy) / n)
+    u = u.astype(NPD[prec]).astype(np.float64)
+    got = step(u)
+    ref, _, _ = b2.step_b2_split(u, n, delta, 1, amp, sigma, 1.0, 1.0, 0.05, 0.01)
+    assert np.max(np.abs(got - ref)) <= (1e-11 if prec == "f64" else 1e-9)
+    assert np.max(np.abs(ref)) < 0.01
+
+
+def test_b2_split_study_lattice_sampled():
+    """The study's f5 model at full batch (1024 samples of 128^2, delta =
+    0.125, xi_h ~ -0.085, FP32 storage), 2 steps: sampled samples against
+    the oracle's trajectory, OoI against each state's mean."""
+    amp, sigma, _ = synth.gaussian_params(0.25)
+    m = synth.Model(128, 0.125, 1, amp, sigma, c_F=1.0, beta2=0.05, tau=0.01)
+    smp = [synth.Sample(0, 1.0, amp, "nuclei", 6, s, synth.draw_theta(synth.rng_for(6, s)))
+           for s in range(1024)]
+    w = synth.Workload("f5", [m], smp, 2, "f32")
+    b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_AUTO)
+    torch.cuda.synchronize()
+    assert torch.all(torch.abs(b.state.float()) <= 1).item()
+    o = b.ooi_host()
+    for i in (0, 511, 1023):
+        s = w.samples[i]
+        u0 = rounded_initial(w, s, "f32")
+        ref, mean, f1 = b2.solve_b2(u0, w.nsteps, m.n, m.delta, m.kernel, s.amp, m.sigma,
+                                    s.c_F, m.beta1, m.beta2, m.tau)
+        got = b.sample_state(i)
+        assert np.max(np.abs(got - ref)) <= 1e-4, i
+        assert abs(o[i, 1] - f1) <= 1e-6 * abs(f1), i
+        assert abs(o[i, 0] - got.mean()) <= 1e-12, i
 
 
 def test_b2_benchmark_workload_sampled():
