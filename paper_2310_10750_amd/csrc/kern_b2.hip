@@ -27,8 +27,9 @@
 // a strictly convex problem (u is the projection of r' onto K in the norm of
 // (tau A)^{-1}) with a unique solution.  It is solved by the primal-dual
 // active-set iteration on the complementarity problem in mu, whose matrix
-// tau A is an M-matrix: the active sets A+ = {mu + (u - 1) > 0} and
-// A- = {mu + (u + 1) < 0} fix u = +-1 there and mu = 0 elsewhere; conjugate
+// tau A is an M-matrix: the active sets A+ = {mu + c (u - 1) > 0} and
+// A- = {mu + c (u + 1) < 0} (c = diag(tau A)) fix u = +-1 there and mu = 0
+// elsewhere; conjugate
 // gradients solve (tau A)_AA mu_A = r'_A - u_A (the rows and columns of the
 // inactive sites removed; warm-started from the previous mu), and the
 // inactive sites take u_I = r'_I - (tau A mu)_I.  The iteration stops when the
@@ -63,9 +64,15 @@ constexpr int kMaxCg = 4000;
 constexpr int kMaxHalvings = 30;
 constexpr int kMaxPdas = 60;
 
-// Active-set code of a site from (u, mu) with c = 1: +1 (A+), -1 (A-), 0.
-__device__ __forceinline__ double pdas_code(double u, double mu) {
-    return mu + (u - 1.0) > 0.0 ? 1.0 : (mu + (u + 1.0) < 0.0 ? -1.0 : 0.0);
+// Active-set code of a site from (u, mu): +1 (A+: mu + c (u - 1) > 0), -1
+// (A-: mu + c (u + 1) < 0), or 0.  Once u = +-1 on the active sites and
+// mu = 0 elsewhere, c only decides whether a site may jump from one bound to
+// the other in one iteration (|mu| > 2c) rather than pass through the
+// inactive set; c = diag(tau A) keeps such jumps to multipliers that are
+// large on the operator's own scale.  (With c = 1 and warm starts, the
+// iteration was seen to cycle on the two-sided constraint.)
+__device__ __forceinline__ double pdas_code(double u, double mu, double c) {
+    return mu + c * (u - 1.0) > 0.0 ? 1.0 : (mu + c * (u + 1.0) < 0.0 ? -1.0 : 0.0);
 }
 
 // Stopping level of a split-step CG solve in the norm s.M^-1 s (M^-1 = d_act
@@ -216,13 +223,14 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
             U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
         }
         __syncthreads();
-        const double d_act = 1.0 / (tb1 + 4.0 * tb2n2);  // Jacobi: one value on the active rows
+        const double c_pd = tb1 + 4.0 * tb2n2;  // diag(tau A)
+        const double d_act = 1.0 / c_pd;         // Jacobi: one value on the active rows
         bool ok = false;
         for (int it = 0;; ++it) {
             // active sets from (u, mu); u = +-1 on them, mu = 0 off them
             double cs[2] = {0.0, 0.0};  // changed sites, |s|^2
             for (int i = tid; i < nn; i += kB2Threads) {
-                const double c = pdas_code(U[i], M[i]);
+                const double c = pdas_code(U[i], M[i], c_pd);
                 if (c != C[i]) cs[0] += 1.0;
                 C[i] = c;
                 if (c != 0.0)
@@ -732,6 +740,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         // code of the last iteration (C) in the workspace; each CG solve
         // accumulates the change of mu in Xl + Xlo
         double *U = Z, *M = F, *C = X;
+        const double c_pd = tb1 + 4.0 * tb2n2;  // diag(tau A)
         for (int i = tid; i < nn; i += kB2LdsThreads) {
             const int y = i / n, x = i - y * n;
             U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
             for (int k = 0; k < SPT; ++k) {
                 const int i = site(k);
                 if (valid(k)) {
-                    const double c = pdas_code(U[i], M[i]);
+                    const double c = pdas_code(U[i], M[i], c_pd);
                     if (c != C[i]) cs[0] += 1.0;
                     C[i] = c;
                     if (c != 0.0) {

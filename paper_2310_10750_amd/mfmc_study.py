@@ -53,9 +53,12 @@ PAPER_BUDGETS_SECONDS = [10 ** (3 + i / 3) for i in range(8)]
 PILOT_SEED, STUDY_SEED, VALIDATION_SEED = 41, 42, 43
 
 
-def study_models(lattices=MODELS9, delta_hf=0.25, tau=0.01):
+def study_models(lattices=MODELS9, delta_hf=0.25, tau=0.01, beta2=0.0):
+    """The study's models; beta2 = 0.05 is the paper's (a coupled step per
+    time step: Newton for xi_h > 0, the split step for the truncated kernels'
+    xi_h <= 0)."""
     amp, sigma, _ = synth.gaussian_params(delta_hf)
-    return [synth.Model(n, delta, synth.KERNEL_GAUSSIAN, amp, sigma, tau=tau)
+    return [synth.Model(n, delta, synth.KERNEL_GAUSSIAN, amp, sigma, beta2=beta2, tau=tau)
             for _, n, delta in lattices]
 
 
@@ -64,9 +67,10 @@ class Runner:
     for given draw indices of a seed, in fixed-size batches on the GPU."""
 
     def __init__(self, models, nsteps=100, precision="f32", chunk=4096, device="cuda:0",
-                 algo=nlch.NLCH_ALGO_AUTO | nlch.NLCH_ALGO_AUTOTUNE, block=4096):
+                 algo=nlch.NLCH_ALGO_AUTO | nlch.NLCH_ALGO_AUTOTUNE, block=4096, log=None):
         import torch
         self.torch = torch
+        self.log = log  # progress lines of long output runs (every ~30 s)
         self.models = models
         self.nsteps = nsteps
         self.prec = precision
@@ -116,7 +120,11 @@ class Runner:
         st, scr, ooi, md, smp = self._buffers(k)
         res = np.empty(idx.size)
         torch = self.torch
+        t_last = time.time()
         for lo in range(0, idx.size, self.chunk):
+            if self.log and time.time() - t_last > 30.0:
+                self.log("  model %d: %d of %d draws" % (k, lo, idx.size))
+                t_last = time.time()
             part = idx[lo:lo + self.chunk]
             # a full batch every time (one batch signature, one graph): the
             # tail repeats the last draw
@@ -177,20 +185,30 @@ def choose_cases(feasible, labels):
 
 
 def run_study(models=None, labels=None, pilot=50, replicates=100, validation=360000,
-              budgets_c1=None, nsteps=100, precision="f32", chunk=4096, log=print):
+              budgets_c1=None, nsteps=100, precision="f32", chunk=4096, log=print,
+              costs_only=False):
     import torch
     models = models or study_models()
     labels = labels or [lab for lab, _, _ in MODELS9]
     K = len(models)
     budgets_c1 = budgets_c1 or [b / PAPER_C1_SECONDS for b in PAPER_BUDGETS_SECONDS]
-    run = Runner(models, nsteps=nsteps, precision=precision, chunk=chunk)
+    run = Runner(models, nsteps=nsteps, precision=precision, chunk=chunk, log=log)
     t0 = time.time()
 
     # 2. pilot statistics and costs
     yp = np.stack([run.outputs(k, PILOT_SEED, np.arange(pilot)) for k in range(K)])
     sigma, rho = pilot_statistics(yp)
-    cost = np.array([run.cost(k) for k in range(K)])
+    cost = np.zeros(K)
+    for k in range(K):
+        cost[k] = run.cost(k)
+        log("cost of %s: %.1f us per sample (%.1fs)" % (labels[k], 1e6 * cost[k],
+                                                         time.time() - t0))
     log("pilot (%d draws) and costs: %.1fs" % (pilot, time.time() - t0))
+    if costs_only:
+        return {"models": [{"label": labels[k], "n": models[k].n, "delta": models[k].delta,
+                            "beta2": models[k].beta2, "rho": float(rho[k]),
+                            "sigma": float(sigma[k]), "cost_s": float(cost[k])}
+                           for k in range(K)], "seconds": time.time() - t0}
 
     # 3. selection
     feasible, ncand = nlch.mfmc_select(list(cost / cost[0]), list(rho))
@@ -259,6 +277,7 @@ def run_study(models=None, labels=None, pilot=50, replicates=100, validation=360
                     "rho": float(rho[k]), "sigma": float(sigma[k]),
                     "cost_s": float(cost[k]), "cost_ratio": float(cost[k] / cost[0])}
                    for k in range(K)],
+        "beta2": models[0].beta2, "nsteps": nsteps, "chunk": chunk,
         "pilot": pilot, "replicates": replicates, "validation": validation,
         "q_validation": q_val, "n_candidates": ncand, "n_feasible": len(feasible),
         "feasible_top": [{"subset": [labels[k] for k in s], "V": V, "bmin_over_c1": bm}
@@ -297,14 +316,25 @@ def main(argv=None):
     ap.add_argument("--replicates", type=int, default=100)
     ap.add_argument("--validation", type=int, default=360000)
     ap.add_argument("--precision", default="f32")
+    ap.add_argument("--beta2", type=float, default=0.0,
+                    help="beta2 of every model (the paper's experiments: 0.05)")
+    ap.add_argument("--budgets", type=int, default=8,
+                    help="use the first N of the paper's 8 budgets")
+    ap.add_argument("--chunk", type=int, default=4096, help="samples per solver call")
+    ap.add_argument("--costs-only", action="store_true",
+                    help="stop after the pilot statistics and the costs")
     ap.add_argument("--out", default=None, help="write the results as JSON here")
     a = ap.parse_args(argv)
-    res = run_study(pilot=a.pilot, replicates=a.replicates, validation=a.validation,
-                    precision=a.precision, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    budgets = [b / PAPER_C1_SECONDS for b in PAPER_BUDGETS_SECONDS[:a.budgets]]
+    res = run_study(models=study_models(beta2=a.beta2), pilot=a.pilot,
+                    replicates=a.replicates, validation=a.validation, budgets_c1=budgets,
+                    precision=a.precision, chunk=a.chunk, costs_only=a.costs_only,
+                    log=lambda *x: print(*x, file=sys.stderr, flush=True))
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)
-    print(report_markdown(res))
+    if not a.costs_only:
+        print(report_markdown(res))
     return 0
 
 
