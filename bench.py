@@ -40,6 +40,8 @@ METRIC = ("site-steps/s & HBM/LDS GB/s: batched FP32 vs 1-sample FP64, "
 # the published 157.3 TFLOP/s with a fused multiply-add counted as one.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
+# FP64 vector: half the FP32 lane rate (the published 78.6 TFLOP/s).
+FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # Rates the peak-measurement program (paper_2310_10750_amd/peaks) reaches on
 # MI355X with this build's flags: FP32 adds, and LDS reads of 8 and 16 bytes
@@ -261,14 +263,20 @@ def main():
     achieved = ops / (solve_ms * 1e-3) / 1e12
     tflops = flops / (solve_ms * 1e-3) / 1e12
     traffic = stored_traffic(kname, w.name)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                "unit": "T lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+    # FP64 arithmetic (FP64 state, or the ACC64 flag) runs at half the lane rate
+    f64 = prec == "f64" or bool(args.algo & nlch.NLCH_ALGO_ACC64)
+    peak_ops = VALU_PEAK_TOPS / 2 if f64 else VALU_PEAK_TOPS
+    peak_tf = FP64_PEAK_TFLOPS if f64 else FP32_PEAK_TFLOPS
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak_ops, 3),
+                "unit": "T lane-ops/s", "frac": round(achieved / peak_ops, 4),
                 "traffic": traffic, "kernel": kname,
+                "arithmetic": "f64" if f64 else "f32",
                 "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel),
                 "flops_per_site_step": algorithmic_flops(mdisc, m0.kernel),
-                "achieved_tflops": round(tflops, 3), "peak_tflops": FP32_PEAK_TFLOPS,
-                "frac_flops": round(tflops / FP32_PEAK_TFLOPS, 4),
-                "frac_measured_add_rate": round(achieved / MEASURED_ADD_TOPS, 4)}
+                "achieved_tflops": round(tflops, 3), "peak_tflops": peak_tf,
+                "frac_flops": round(tflops / peak_tf, 4)}
+    if not f64:
+        roofline["frac_measured_add_rate"] = round(achieved / MEASURED_ADD_TOPS, 4)
     if any(mm.beta2 > 0 for mm in w.models):
         # an iterative solve per step (Newton with conjugate-gradient inner
         # solves): no fixed algorithmic count per site-step to price
@@ -290,7 +298,8 @@ def main():
         # the pipe nearer its ceiling: VALU against the measured add rate, LDS
         # against the measured rate of the kernel's read width
         f_lds = gbs / MEASURED_LDS_GBS[width]
-        roofline["binding_pipe"] = "lds" if f_lds > roofline["frac_measured_add_rate"] else "valu"
+        f_valu = roofline.get("frac_measured_add_rate", roofline["frac"])
+        roofline["binding_pipe"] = "lds" if f_lds > f_valu else "valu"
         roofline["frac_lds"] = round(f_lds, 4)
 
     out = {
@@ -302,6 +311,10 @@ def main():
                    "n": [mm.n for mm in w.models], "R2": R2, "disc_points": N,
                    "time_steps": w.nsteps, "precision": prec, "algo": args.algo},
         "roofline": roofline,
+        # one solve's wall time on the device per time step (for a single
+        # sample: the latency of one step of the high-fidelity model)
+        "latency": {"us_per_time_step": round(1e3 * solve_ms / max(1, w.nsteps), 3),
+                    "samples": S, "time_steps": w.nsteps},
         "hbm_state_gbs": round(hbm_gbs, 1),
         "lds": lds,
     }

@@ -129,14 +129,21 @@ extern "C" {
                                     streaming kernel's launch shapes (lanes'
                                     columns, band height, waves per band) on
                                     the caller's buffers (reads state, writes
-                                    scratch), keep the fastest (cached per
-                                    process); synchronises hip_stream.  Shapes
-                                    that split a band over several waves sum
-                                    the outputs next to the split points in
-                                    two parts: results can differ from the
-                                    default shape by rounding only.  Without
-                                    this flag the shape is a fixed function
-                                    of the batch, so results repeat exactly. */
+                                    scratch), and the resident kernel's
+                                    layouts (see nlch_set_resident_shape) on
+                                    a copy of the states in a temporary
+                                    device buffer (min(nsteps, 10) steps);
+                                    keep the fastest (cached per process);
+                                    synchronises hip_stream (the resident
+                                    layouts are not tuned while hip_stream is
+                                    being captured).  Shapes that split a band
+                                    over several waves, and resident layouts
+                                    other than the default, sum some outputs
+                                    in a different grouping: results can
+                                    differ from the default by rounding only.
+                                    Without this flag the shape is a fixed
+                                    function of the batch, so results repeat
+                                    exactly. */
 
 /* Domain of a model. */
 #define NLCH_BOUNDARY_PERIODIC 0 /* periodic unit square, state n x n          */
@@ -295,8 +302,9 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
 
 /* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
- * calls in this process: each lane owns cols_per_lane adjacent columns and
- * walks rows_per_lane rows of a 16-row band.
+ * calls in this process, overriding the default and NLCH_ALGO_AUTOTUNE.
+ * 128^2 lattices (FP32 state, periodic domain): each lane owns cols_per_lane
+ * adjacent columns and walks rows_per_lane rows of a 16-row band.
  *   (2, 16): one band per wave; every resident case.
  *   (4, 16): two bands per wave (one per half-wave), 16-byte LDS window
  *            loads; bit-identical to (2, 16).
@@ -305,10 +313,19 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
  *            so that a CU's two resident samples give four waves per SIMD.
  *            Band sums are formed in two parts, so results differ from
  *            (2, 16) by FP32 rounding only.
- *   (0, 0):  the default, (4, 8) where built, else (2, 16).
- * The four-column layouts are built for FP32 state on 128^2 lattices of the
- * periodic domain without the energy trace.  Host only; NLCH_EINVAL for other
- * values. */
+ * 64^2 lattices (FP32 state, periodic domain): one column per lane, one band
+ * of rows_per_lane rows per wave:
+ *   (1, 8) (discs with m <= 8), (1, 16), (1, 32): 8, 4 or 2 waves per
+ *            sample.  The partial sums a band hands to its neighbours group
+ *            the disc rows differently, so results differ from (1, 16) by
+ *            FP32 rounding only.
+ * A shape applies to the groups of the lattice it names; other groups, and
+ * cases a layout is not built for, keep their default.
+ *   (0, 0):  the default: (4, 8) on 128^2 where built, else 16-row bands
+ *            ((2, 16) on 128^2, (1, 16) on 64^2); with NLCH_ALGO_AUTOTUNE,
+ *            the layout timed fastest for the batch signature.
+ * With the energy trace the same layouts run.  Host only; NLCH_EINVAL for
+ * other values. */
 int nlch_set_resident_shape(int32_t cols_per_lane, int32_t rows_per_lane);
 
 /* Multifidelity Monte Carlo estimate (Sec. 3.2) from K model outputs.
@@ -371,6 +388,16 @@ int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *nlch_last_error(void);
+
+/* Failure injection, for tests of callers' and the library's error handling
+ * (host only): the nth checked HIP runtime call the library makes from now on
+ * (nth >= 1; counted over all threads) is not made and reports failure, so
+ * the entry point that reaches it returns NLCH_EDEVICE with a message that
+ * contains "injected"; nth = 0 disarms.  Nothing is issued to the device in
+ * place of the skipped call, and the library stays usable: work enqueued
+ * before the failure may have run on the caller's buffers, later calls work
+ * as usual.  NLCH_EINVAL for nth < 0. */
+int nlch_debug_inject_device_error(int32_t nth);
 
 /* ABI version: 5 (increments on any change to a struct, constant or function
  * signature declared here). */

@@ -19,7 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nlch_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# NLCH_ORACLE_LIB selects another build of the same source (the tests'
+# AddressSanitizer/UBSan build).
+_LIB_PATH = os.environ.get("NLCH_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 KERNEL_CONSTANT = 0
 KERNEL_GAUSSIAN = 1
@@ -36,6 +38,17 @@ def build(force: bool = True) -> str:
              _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path: str) -> str:
+    """Compile ``nlch_oracle.c`` with AddressSanitizer and UBSan (gcc; every
+    undefined-behaviour report fatal) into ``path``, for a test process that
+    preloads gcc's ASan runtime and sets NLCH_ORACLE_LIB."""
+    subprocess.check_call(
+        ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+         "-fno-sanitize-recover=all", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+         _SRC, "-o", path, "-lm"])
+    return path
 
 
 def _load():

@@ -30,6 +30,10 @@ COMMON = [
 ]
 
 
+# roctx ranges around graph capture and replay (rocprofv3 --marker-trace)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
@@ -65,6 +69,53 @@ def _stale(src):
     return max(os.path.getmtime(f) for f in deps) > os.path.getmtime(obj)
 
 
+# Host units of the C ABI (argument validation, tables, batches, graphs,
+# MFMC selection): the ones the host sanitizer build instruments.
+HOST_UNITS = ("nlch_api.cpp", "mfmc_select.cpp", "nlch_noalloc.cpp")
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def asan_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (to preload into a
+    process that loads the host sanitizer build)."""
+    r = subprocess.run([HIPCC, "--print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else ""
+
+
+def build_host_sanitized(path: str, verbose: bool = False) -> str:
+    """The library with its host units compiled with AddressSanitizer and
+    UBSan (host code only; device code as in the normal build), linked with
+    the normal build's kernel objects into ``path``.  Needs a completed
+    build()."""
+    objs = []
+    for src in sources():
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        if src in HOST_UNITS:
+            sobj = os.path.join(os.path.dirname(path), os.path.splitext(src)[0] + ".san.o")
+            extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+            cmd = [HIPCC, "-x", "hip"] + COMMON + extra + SAN_HOST + [
+                "-c", os.path.join(CSRC, src), "-o", sobj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError("hipcc (sanitized) failed on %s:\n%s" % (src, r.stderr))
+            objs.append(sobj)
+        else:
+            if not os.path.exists(obj):
+                raise RuntimeError("%s is not built: run build() first" % obj)
+            objs.append(obj)
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", path] + objs + LINK + [
+        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+        "-shared-libsan"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stdout + r.stderr)
+    return path
+
+
 PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
 PEAKS = os.path.join(HERE, "peaks", "nlch_peaks")
 
@@ -98,7 +149,7 @@ def build(verbose: bool = True, jobs: int = None, incremental: bool = False) -> 
             if rc != 0:
                 raise RuntimeError("hipcc failed on %s:\n%s" % (src, log))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + LINK
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -62,15 +62,18 @@ constexpr int kB2Waves = kB2Threads / 64;
 constexpr int kMaxNewton = 40;
 constexpr int kMaxCg = 4000;
 constexpr int kMaxHalvings = 30;
-constexpr int kMaxPdas = 60;
+constexpr int kPdasPhase = 20;  // active-set iterations per start (three starts at most)
 
 // Active-set code of a site from (u, mu): +1 (A+: mu + c (u - 1) > 0), -1
 // (A-: mu + c (u + 1) < 0), or 0.  Once u = +-1 on the active sites and
 // mu = 0 elsewhere, c only decides whether a site may jump from one bound to
 // the other in one iteration (|mu| > 2c) rather than pass through the
-// inactive set; c = diag(tau A) keeps such jumps to multipliers that are
-// large on the operator's own scale.  (With c = 1 and warm starts, the
-// iteration was seen to cycle on the two-sided constraint.)
+// inactive set.  On the two-sided constraint the iteration can cycle from
+// some starts for any fixed c (the M-matrix convergence result covers
+// one-sided obstacles), so a step makes up to three starts of kPdasPhase
+// iterations each: from the previous step's mu with c = diag(tau A) (within
+// a call), then from mu = 0, u = r' with c = diag(tau A), then from mu = 0,
+// u = r' with c = 1.
 __device__ __forceinline__ double pdas_code(double u, double mu, double c) {
     return mu + c * (u - 1.0) > 0.0 ? 1.0 : (mu + c * (u + 1.0) < 0.0 ? -1.0 : 0.0);
 }
@@ -223,10 +226,12 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
             U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
         }
         __syncthreads();
-        const double c_pd = tb1 + 4.0 * tb2n2;  // diag(tau A)
-        const double d_act = 1.0 / c_pd;         // Jacobi: one value on the active rows
+        const double diag = tb1 + 4.0 * tb2n2;  // diag(tau A)
+        const double d_act = 1.0 / diag;         // Jacobi: one value on the active rows
+        int start = warm ? 0 : 1, start_it = 0;  // see pdas_code
+        double c_pd = diag;
         bool ok = false;
-        for (int it = 0;; ++it) {
+        for (;;) {
             // active sets from (u, mu); u = +-1 on them, mu = 0 off them
             double cs[2] = {0.0, 0.0};  // changed sites, |s|^2
             for (int i = tid; i < nn; i += kB2Threads) {
@@ -253,7 +258,20 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
                 ok = true;
                 break;
             }
-            if (it == kMaxPdas) break;
+            if (++start_it == kPdasPhase) {
+                // no settled sets from this start: the next one, from mu = 0
+                if (start == 2) break;
+                ++start;
+                start_it = 0;
+                c_pd = start == 2 ? 1.0 : diag;
+                for (int i = tid; i < nn; i += kB2Threads) {
+                    M[i] = 0.0;
+                    U[i] = R[i];
+                    C[i] = 2.0;
+                }
+                __syncthreads();
+                continue;
+            }
             // CG on (tau A)_AA from the current mu (directions vanish on the
             // inactive sites)
             double rz = cs[1] * d_act;
@@ -740,13 +758,15 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
         // code of the last iteration (C) in the workspace; each CG solve
         // accumulates the change of mu in Xl + Xlo
         double *U = Z, *M = F, *C = X;
-        const double c_pd = tb1 + 4.0 * tb2n2;  // diag(tau A)
+        const double diag = uniform_f64(tb1 + 4.0 * tb2n2);  // diag(tau A)
+        int start = warm ? 0 : 1, start_it = 0;  // see pdas_code
+        double c_pd = diag;
         for (int i = tid; i < nn; i += kB2LdsThreads) {
             const int y = i / n, x = i - y * n;
             U[i] = warm ? R[i] - tau_a(M, i, y, x, n, nn, tb1, tb2n2) : R[i];
         }
         __syncthreads();
-        for (int it = 0;; ++it) {
+        for (;;) {
             // active sets from (u, mu); u = +-1 on them, mu = 0 off them
             double cs[2] = {0.0, 0.0};  // changed sites, |s|^2
             unsigned mask = 0;          // bit k: site t + THREADS k inactive
@@ -794,7 +814,20 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
                 ok = true;
                 break;
             }
-            if (it == kMaxPdas) break;
+            if (++start_it == kPdasPhase) {
+                // no settled sets from this start: the next one, from mu = 0
+                if (start == 2) break;
+                ++start;
+                start_it = 0;
+                c_pd = start == 2 ? 1.0 : diag;
+                for (int i = tid; i < nn; i += kB2LdsThreads) {
+                    M[i] = 0.0;
+                    U[i] = R[i];
+                    C[i] = 2.0;
+                }
+                __syncthreads();
+                continue;
+            }
             const double rz = cs[1] * d_act;
             cg(mask, Sr, Xlo, rz, pdas_cg_stop(rz, d_act, scale, cs[0] != 0.0));
 #pragma unroll

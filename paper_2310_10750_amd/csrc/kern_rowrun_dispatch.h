@@ -76,14 +76,26 @@ hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t 
 // or two (n = 128) adjacent columns; built for these two lattice sizes.
 constexpr int kResB = 16;
 
+// Band height of a resident group: 16 rows, or for FP32 64^2 periodic
+// lattices the 8 or 32 rows that nlch_set_resident_shape or the autotuner
+// chose (m <= B: partial sums only reach the adjacent bands).
+template <class TS, class TA>
+int resident_band_rows(const Group &g, int M, bool vol) {
+    if (std::is_same<TS, float>::value && std::is_same<TA, float>::value && g.ni == 64 &&
+        !vol && (g.res_rows == 8 || g.res_rows == 32) && M <= g.res_rows)
+        return g.res_rows;
+    return kResB;
+}
+
 template <int R2, class TS, class TA, bool GAUSS>
 hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
                            hipStream_t s, double *energy, int64_t estride) {
     constexpr int M = Disc<R2>::M;
     const bool vol = g.lo != 0;  // Omega's g.ni x g.ni lattice inside a ring of m
-    const int threads = 64 * (g.ni / kResB);
+    const int B = resident_band_rows<TS, TA>(g, M, vol);
+    const int threads = 64 * (g.ni / B);
     const size_t lds =
-        resident_lds_bytes(g.ni, M, kResB, sizeof(TS), sizeof(TA), energy != nullptr, vol);
+        resident_lds_bytes(g.ni, M, B, sizeof(TS), sizeof(TA), energy != nullptr, vol);
     if ((g.ni != 64 && g.ni != 128) || (vol && (g.lo != M || energy)) ||
         lds > kLdsBytes - 1024)
         return hipErrorInvalidValue;
@@ -107,6 +119,14 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
         // the plain solve)
         if (g.ni == 128 && g.res_cols != 2 && resident4_built(g.R2))
             return resident4_launch_f32(g, state, nsteps, ooi, s, energy, estride);
+        if constexpr (M <= 8) {
+            if (g.ni == 64 && B == 8)
+                return energy ? go(k_resident<R2, 64, 8, TS, TA, GAUSS, true, false>)
+                              : go(k_resident<R2, 64, 8, TS, TA, GAUSS, false, false>);
+        }
+        if (g.ni == 64 && B == 32)
+            return energy ? go(k_resident<R2, 64, 32, TS, TA, GAUSS, true, false>)
+                          : go(k_resident<R2, 64, 32, TS, TA, GAUSS, false, false>);
     }
     if (energy)
         return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>)

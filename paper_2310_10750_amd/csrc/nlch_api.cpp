@@ -2,8 +2,10 @@
 // geometry and kernel tables, per-sample coefficients, launch grouping, and
 // HIP-graph capture/replay of whole solves.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -103,6 +105,22 @@ int nlch::fail(int code, const char *fmt, ...) {
 }
 
 int nlch::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+// Checked HIP calls still to be made before the injected failure (0: none
+// armed).  The armed call reports failure without being made, so nothing
+// invalid reaches the device.
+static std::atomic<int64_t> g_inject{0};
+
+bool nlch::inject_device_error() {
+    if (g_inject.load(std::memory_order_relaxed) <= 0) return false;
+    return g_inject.fetch_sub(1) == 1;
+}
+
+// Scope of a named roctx range (visible to rocprofv3 --marker-trace).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+};
 
 // ---------------------------------------------------------------- geometry --
 
@@ -363,6 +381,7 @@ struct Batch {
 constexpr int kAuxStreams = 3;
 
 struct DevCtx {
+    bool ready = false;  // every resource below created
     hipStream_t capture = nullptr;
     hipStream_t aux[kAuxStreams] = {};
     hipEvent_t fork = nullptr;
@@ -383,18 +402,23 @@ int dev_ctx(DevCtx **out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     DevCtx &c = g_dev[dev];
-    if (!c.capture) {
-        HIP_TRY(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+    if (!c.ready) {
+        // each resource once: a failure part-way leaves the rest to the next call
+        if (!c.capture) HIP_TRY(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
         for (int i = 0; i < kAuxStreams; ++i) {
-            HIP_TRY(hipStreamCreateWithFlags(&c.aux[i], hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
+            if (!c.aux[i]) HIP_TRY(hipStreamCreateWithFlags(&c.aux[i], hipStreamNonBlocking));
+            if (!c.join[i]) HIP_TRY(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
         }
-        HIP_TRY(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
-        HIP_TRY(hipMalloc((void **)&c.counter, sizeof(unsigned int)));
-        HIP_TRY(hipHostMalloc((void **)&c.counter_h, sizeof(unsigned int), hipHostMallocDefault));
-        HIP_TRY(hipMalloc((void **)&c.mom, sizeof(double) * 8 * NLCH_MFMC_MAX_K));
-        HIP_TRY(hipHostMalloc((void **)&c.mom_h, sizeof(double) * 8 * NLCH_MFMC_MAX_K,
-                              hipHostMallocDefault));
+        if (!c.fork) HIP_TRY(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+        if (!c.counter) HIP_TRY(hipMalloc((void **)&c.counter, sizeof(unsigned int)));
+        if (!c.counter_h)
+            HIP_TRY(hipHostMalloc((void **)&c.counter_h, sizeof(unsigned int),
+                                  hipHostMallocDefault));
+        if (!c.mom) HIP_TRY(hipMalloc((void **)&c.mom, sizeof(double) * 8 * NLCH_MFMC_MAX_K));
+        if (!c.mom_h)
+            HIP_TRY(hipHostMalloc((void **)&c.mom_h, sizeof(double) * 8 * NLCH_MFMC_MAX_K,
+                                  hipHostMallocDefault));
+        c.ready = true;
     }
     *out = &c;
     return NLCH_OK;
@@ -651,6 +675,102 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
     return NLCH_OK;
 }
 
+// Resident layout of a group from nlch_set_resident_shape: the forced shape
+// where it names this group's lattice (cols 2 or 4: 128^2; cols 1: 64^2).
+bool forced_resident_shape(const Group &g, int *cols, int *rows) {
+    const int c = g_force_res_cols, r = g_force_res_rows;
+    if (c == 0) return false;
+    const bool fits = (g.ni == 128 && (c == 2 || c == 4)) || (g.ni == 64 && c == 1);
+    *cols = fits ? c : 0;
+    *rows = fits ? r : 0;
+    return true;
+}
+
+// Autotuner of the resident layout, cached per (device, precision, disc,
+// kernel, lattice, group size): FP32 periodic groups of 128^2 time (2, 16),
+// (4, 16) and (4, 8); of 64^2, bands of 8 (m <= 8), 16 and 32 rows.  Each
+// candidate runs min(nsteps, 10) steps of the whole group -- once to warm
+// up, then twice timed (the faster counts) -- on a copy of the caller's
+// states in a buffer of the tuner's own, which it frees afterwards.
+struct ResTune {
+    int cols, rows;
+};
+std::map<TuneKey, ResTune> g_tuned_res;
+
+int autotune_resident(Group &g, int dev, int prec, bool acc64, const nlch_sample *samples,
+                      int64_t n_samples, const void *state, int nsteps, hipStream_t s) {
+    g.res_cols = g.res_rows = 0;
+    std::vector<ResTune> cands;
+    if (prec == kF32 && !acc64 && g.lo == 0) {
+        if (g.ni == 128 && resident4_built(g.R2)) cands = {{2, 16}, {4, 16}, {4, 8}};
+        if (g.ni == 64) {
+            if (g.m <= 8) cands.push_back({1, 8});
+            cands.push_back({1, 16});
+            cands.push_back({1, 32});
+        }
+    }
+    if (cands.empty() || nsteps < 1) return NLCH_OK;
+    const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.lo, g.nids};
+    auto it = g_tuned_res.find(key);
+    if (it != g_tuned_res.end()) {
+        g.res_cols = it->second.cols;
+        g.res_rows = it->second.rows;
+        return NLCH_OK;
+    }
+    int64_t end = 0;  // elements of the state buffer the group's samples span
+    for (int64_t i = 0; i < n_samples; ++i)
+        if (samples[i].model == g.model)
+            end = std::max<int64_t>(end, samples[i].offset + (int64_t)g.n * g.n);
+    void *tmp = nullptr;
+    double *tooi = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (tmp) (void)hipFree(tmp);
+        if (tooi) (void)hipFree(tooi);
+    };
+    int rc = [&]() -> int {
+        HIP_TRY(hipMalloc(&tmp, (size_t)end * prec_size(prec)));
+        HIP_TRY(hipMalloc((void **)&tooi, sizeof(double) * 2 * (size_t)n_samples));
+        HIP_TRY(hipMemcpyAsync(tmp, state, (size_t)end * prec_size(prec),
+                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        const int nt = nsteps < 10 ? nsteps : 10;
+        float best = 1e30f;
+        ResTune pick{0, 0};
+        for (const ResTune &c : cands) {
+            g.res_cols = c.cols;
+            g.res_rows = c.rows;
+            HIP_TRY(launch_resident(prec, acc64, g, tmp, nt, tooi, s, nullptr, 0));
+            for (int r = 0; r < 2; ++r) {
+                HIP_TRY(hipEventRecord(e0, s));
+                HIP_TRY(launch_resident(prec, acc64, g, tmp, nt, tooi, s, nullptr, 0));
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    pick = c;
+                }
+            }
+        }
+        g.res_cols = pick.cols;
+        g.res_rows = pick.rows;
+        g_tuned_res[key] = pick;
+        if (std::getenv("NLCH_VERBOSE"))
+            std::fprintf(stderr, "nlch autotune (resident): n=%d R2=%d samples=%d -> "
+                         "cols=%d rows=%d (%.3f ms per %d steps)\n", g.n, g.R2, g.nids,
+                         pick.cols, pick.rows, best, nt);
+        return NLCH_OK;
+    }();
+    cleanup();
+    if (rc) g.res_cols = g.res_rows = 0;
+    return rc;
+}
+
 hipError_t launch_step(int variant, int prec, bool acc64, const Group &g, const void *in,
                        void *out, hipStream_t s, double *epart = nullptr, bool warm = false) {
     if (variant == kRowrun) return launch_rowrun_step(prec, acc64, g, in, out, s, epart);
@@ -764,20 +884,35 @@ int enqueue_solve(Batch &b, DevCtx &ctx, int prec, bool acc64, int nsteps, void 
         return enqueue_group(b, 0, prec, acc64, nsteps, state, scratch, ooi, energy, estride, s);
     const int naux = (int)std::min<size_t>(G - 1, (size_t)kAuxStreams);
     HIP_TRY(hipEventRecord(ctx.fork, s));
-    for (int i = 0; i < naux; ++i) HIP_TRY(hipStreamWaitEvent(ctx.aux[i], ctx.fork, 0));
+    int forked = 0, rc = NLCH_OK;
+    for (; forked < naux && !rc; ++forked) {
+        if (inject_device_error()) {
+            rc = fail(NLCH_EDEVICE, "hipStreamWaitEvent(aux): injected device error");
+            break;
+        }
+        const hipError_t e = hipStreamWaitEvent(ctx.aux[forked], ctx.fork, 0);
+        if (e != hipSuccess) {
+            rc = fail(NLCH_EDEVICE, "hipStreamWaitEvent(aux): %s", hipGetErrorString(e));
+            break;
+        }
+    }
     // group 0 (the first model, the high-fidelity level in an MFMC batch) on
     // the caller's stream, the rest round-robin on the auxiliary streams
-    for (size_t gi = 0; gi < G; ++gi) {
+    for (size_t gi = 0; gi < G && !rc; ++gi) {
         hipStream_t sg = gi == 0 ? s : ctx.aux[(gi - 1) % naux];
-        int rc = enqueue_group(b, gi, prec, acc64, nsteps, state, scratch, ooi, energy,
-                               estride, sg);
-        if (rc) return rc;
+        rc = enqueue_group(b, gi, prec, acc64, nsteps, state, scratch, ooi, energy, estride,
+                           sg);
     }
-    for (int i = 0; i < naux; ++i) {
-        HIP_TRY(hipEventRecord(ctx.join[i], ctx.aux[i]));
-        HIP_TRY(hipStreamWaitEvent(s, ctx.join[i], 0));
+    // Join every forked stream back into s, after a failure too: a capture
+    // must end joined, and later work on s must follow what the auxiliary
+    // streams already hold.  (Not subject to failure injection.)
+    for (int i = 0; i < forked; ++i) {
+        hipError_t e = hipEventRecord(ctx.join[i], ctx.aux[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx.join[i], 0);
+        if (e != hipSuccess && !rc)
+            rc = fail(NLCH_EDEVICE, "joining the auxiliary streams: %s", hipGetErrorString(e));
     }
-    return NLCH_OK;
+    return rc;
 }
 
 }  // namespace
@@ -884,6 +1019,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         }
         b->tuned = false;
     } else if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
+        TraceRange tr("nlch autotune");
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
             if (b->variant[gi] != kRowrun) continue;
             rc = autotune_group(b->groups[gi], b->device, precision, acc64, state, scratch, s);
@@ -894,10 +1030,18 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         for (Group &g : b->groups) set_shape(g, {0, 0, 0, 0});
     }
 
+    // resident layouts: forced (nlch_set_resident_shape), tuned, or default
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        const bool res = b->variant[gi] == kResident;
-        b->groups[gi].res_cols = res ? g_force_res_cols : 0;
-        b->groups[gi].res_rows = res ? g_force_res_rows : 0;
+        Group &g = b->groups[gi];
+        g.res_cols = g.res_rows = 0;
+        if (b->variant[gi] != kResident || forced_resident_shape(g, &g.res_cols, &g.res_rows))
+            continue;
+        if ((algo & NLCH_ALGO_AUTOTUNE) && !capturing) {
+            TraceRange tr("nlch autotune (resident)");
+            rc = autotune_resident(g, b->device, precision, acc64, samples, n_samples, state,
+                                   nsteps, s);
+            if (rc) return rc;
+        }
     }
 
     if (energy_out) {
@@ -908,6 +1052,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
     if (rc) return rc;
 
     if (algo & NLCH_ALGO_NOGRAPH) {
+        TraceRange tr("nlch enqueue (no graph)");
         rc = enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
                            energy_out, n_samples, s);
         if (rc) return rc;
@@ -938,6 +1083,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
             for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
             b->graphs.clear();
         }
+        TraceRange tr("nlch graph capture");
         HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
         rc = enqueue_solve(*b, *ctx, precision, acc64, nsteps, state, scratch, ooi_out,
                            energy_out, n_samples, ctx->capture);
@@ -945,18 +1091,26 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
         if (rc) {
             if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();  // the error is reported here, not to the next HIP call
             return rc;
         }
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
             return fail(NLCH_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        }
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
             return fail(NLCH_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
         it = b->graphs.emplace(gk, exec).first;
     }
-    HIP_TRY(hipGraphLaunch(it->second, s));
+    {
+        TraceRange tr("nlch graph replay");
+        HIP_TRY(hipGraphLaunch(it->second, s));
+    }
     return batch_end(*b, s, capturing);
 }
 
@@ -967,6 +1121,12 @@ extern "C" {
 int nlch_version(void) { return 5; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
+
+int nlch_debug_inject_device_error(int32_t nth) {
+    if (nth < 0) return fail(NLCH_EINVAL, "nth must be >= 0 (0 disarms)");
+    g_inject.store(nth);
+    return NLCH_OK;
+}
 
 int nlch_rowrun_supported(int32_t precision, int64_t *r2_list, int32_t cap) {
     if (precision < NLCH_F64 || precision > NLCH_F16_STORE)
@@ -1081,9 +1241,11 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
 
 int nlch_set_resident_shape(int32_t cols_per_lane, int32_t rows_per_lane) {
     const int c = cols_per_lane, r = rows_per_lane;
-    if (!((c == 0 && r == 0) || (c == 2 && r == 16) || (c == 4 && (r == 16 || r == 8))))
+    if (!((c == 0 && r == 0) || (c == 2 && r == 16) || (c == 4 && (r == 16 || r == 8)) ||
+          (c == 1 && (r == 8 || r == 16 || r == 32))))
         return fail(NLCH_EINVAL, "resident shape must be (0, 0) (default), (2, 16), (4, 16) or "
-                    "(4, 8) columns and rows per lane");
+                    "(4, 8) (128^2), or (1, 8), (1, 16) or (1, 32) (64^2) columns and rows "
+                    "per lane");
     std::lock_guard<std::mutex> lk(g_mu);
     g_force_res_cols = c;
     g_force_res_rows = r;

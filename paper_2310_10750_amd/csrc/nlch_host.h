@@ -17,11 +17,24 @@ namespace nlch {
 // returns code.
 int fail(int code, const char *fmt, ...);
 
+// Failure injection (nlch_debug_inject_device_error): true for the one
+// checked HIP call that is to report failure instead of being made.
+bool inject_device_error();
+
+// A checked HIP runtime call: its failure (or an injected one, in which case
+// the call is not made) returns NLCH_EDEVICE from the enclosing function.  The
+// error is reported through the library's code and message, and cleared from
+// HIP's per-thread last error, so that it does not resurface at the caller's
+// next, unrelated HIP call.
 #define HIP_TRY(expr)                                                             \
     do {                                                                          \
+        if (::nlch::inject_device_error())                                        \
+            return ::nlch::fail(NLCH_EDEVICE, "%s: injected device error", #expr); \
         hipError_t e_ = (expr);                                                   \
-        if (e_ != hipSuccess)                                                     \
+        if (e_ != hipSuccess) {                                                   \
+            (void)hipGetLastError();                                              \
             return ::nlch::fail(NLCH_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+        }                                                                         \
     } while (0)
 
 // A validated model's disc and kernel tables.

@@ -12,7 +12,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnlch.so")
+# NLCH_LIB_PATH selects another build of the same library (the tests' host
+# sanitizer build).
+LIB_PATH = os.environ.get("NLCH_LIB_PATH") or os.path.join(_HERE, "libnlch.so")
 
 NLCH_OK = 0
 NLCH_EINVAL = -1
@@ -132,6 +134,8 @@ def load():
     lib.nlch_last_error.restype = ctypes.c_char_p
     lib.nlch_version.argtypes = []
     lib.nlch_version.restype = ctypes.c_int
+    lib.nlch_debug_inject_device_error.argtypes = [i32]
+    lib.nlch_debug_inject_device_error.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -163,6 +167,11 @@ def nlch_last_error() -> str:
 
 def nlch_version() -> int:
     return load().nlch_version()
+
+
+def nlch_debug_inject_device_error(nth: int) -> None:
+    """Make the nth checked HIP call from now on fail (0 disarms)."""
+    _check(load().nlch_debug_inject_device_error(nth))
 
 
 def nlch_rowrun_supported(precision: int = 1):

@@ -234,3 +234,33 @@ def test_volume_constraint_validation(orc):
     assert _err(f, [vol], S, 5, 1, 0, big, None, big * 3) == E
     # nlch_step: buffers n^2 FP32 elements apart overlap with the ring
     assert _err(nlch.nlch_step, vol, 1, 0, 4096, 4096 + 4 * n * n) == E
+
+
+def test_device_error_injection_switch():
+    """The failure-injection switch: armed for the first checked HIP call, a
+    solve with valid arguments returns NLCH_EDEVICE naming the injection
+    (its device query is the call skipped); the switch is then spent, and it
+    rejects a negative count."""
+    md = _good_model()
+    S = [nlch.nlch_sample(0, 0, 1.0, 1.0, 0)]
+    b = 1 << 30
+    try:
+        nlch.nlch_debug_inject_device_error(1)
+        assert _err(nlch.nlch_solve_batch, [md], S, 5, 1, 0, b, 2 * b,
+                    3 * b) == nlch.NLCH_EDEVICE
+        assert "injected" in nlch.nlch_last_error()
+        assert "hipGetDevice" in nlch.nlch_last_error()
+        # spent: without a GPU the next solve fails at the same call, for real
+        assert _err(nlch.nlch_solve_batch, [md], S, 5, 1, 0, b, 2 * b,
+                    3 * b) == nlch.NLCH_EDEVICE
+        assert "injected" not in nlch.nlch_last_error()
+        # validation errors come before any HIP call: an armed switch is kept
+        nlch.nlch_debug_inject_device_error(1)
+        assert _err(nlch.nlch_solve_batch, [md], S, -1, 1, 0, b, 2 * b,
+                    3 * b) == nlch.NLCH_EINVAL
+        assert _err(nlch.nlch_solve_batch, [md], S, 5, 1, 0, b, 2 * b,
+                    3 * b) == nlch.NLCH_EDEVICE
+        assert "injected" in nlch.nlch_last_error()
+        assert _err(nlch.nlch_debug_inject_device_error, -1) == nlch.NLCH_EINVAL
+    finally:
+        nlch.nlch_debug_inject_device_error(0)

@@ -34,10 +34,12 @@ def test_roofline_labels_in_source():
     FLOP-based fraction against the published 157.3 TFLOP/s, the LDS
     fractions against both measured read rates and the binding pipe."""
     src = open(os.path.join(ROOT, "bench.py")).read()
-    for key in ('"unit": "T lane-ops/s"', '"frac_flops"', '"peak_tflops": FP32_PEAK_TFLOPS',
-                '"frac_measured_8B"', '"frac_measured_16B"', '"binding_pipe"'):
+    for key in ('"unit": "T lane-ops/s"', '"frac_flops"', '"peak_tflops": peak_tf',
+                '"frac_measured_8B"', '"frac_measured_16B"', '"binding_pipe"',
+                '"us_per_time_step"', '"arithmetic"'):
         assert key in src, key
     assert bench.FP32_PEAK_TFLOPS == 157.3
+    assert bench.FP64_PEAK_TFLOPS == 78.6
     assert abs(bench.VALU_PEAK_TOPS - 78.6432) < 1e-3
 
 

@@ -10,6 +10,14 @@ nlch_set_resident_shape(columns, rows per lane):
   is checked against the FP64 oracle at every site, and against (2, 16)
   along a trajectory.
 
+64^2 lattices (FP32) run one column per lane with bands of 8 (m <= 8), 16 or
+32 rows, set with (1, 8), (1, 16), (1, 32): the partial sums handed between
+bands group the disc rows differently, so they differ by FP32 rounding; each
+is checked against the FP64 oracle at every site and against (1, 16) along
+a trajectory.  NLCH_ALGO_AUTOTUNE picks one of the layouts per batch
+signature; its results stay within rounding of the default and repeat
+exactly once the pick is cached.
+
 The outputs of interest are FP64 sums of the states in a layout-dependent
 order, so for bit-identical states they agree to FP64 rounding."""
 import math
@@ -105,3 +113,60 @@ def test_benchmark_workload_layouts_agree(orc):
     ref = oracle_samples(orc, w, [0, 1, 255], "f32")
     for i in (0, 1, 255):
         assert abs(out[(4, 8)][1][i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2])
+
+
+SHAPES64 = [(1, 8), (1, 16), (1, 32)]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("R2", [1, 4, 9, 16, 25, 64])
+def test_band_heights_of_the_64sq_resident_kernel(orc, R2, kind):
+    print("64^2 band heights R2=%d kernel=%d" % (R2, kind), flush=True)
+    n, S = 64, 6
+    md = _model(n, R2, kind)
+    rng = np.random.default_rng(R2 * 7 + kind)
+    host = rng.uniform(-1.2, 1.2, S * n * n).astype(np.float32)
+    smp = [nlch.nlch_sample(0, 0, 0.97 + 0.01 * k, md.kernel_amp, k * n * n) for k in range(S)]
+    for nsteps in (1, 30):
+        out = {sh: _solve(md, smp, host, nsteps, sh) for sh in SHAPES64}
+        base, obase = out[(1, 16)]
+        for sh in SHAPES64:
+            st, oo = out[sh]
+            assert np.max(np.abs(st.astype(np.float64) - base)) <= \
+                (1e-6 if nsteps == 1 else 1e-4), sh
+            for k in range(S):
+                assert abs(oo[2 * k] - np.mean(st[k * n * n:(k + 1) * n * n].astype(np.float64))) \
+                    <= 1e-12
+            if nsteps == 1:
+                for k in (0, S - 1):
+                    u0 = np.clip(host[k * n * n:(k + 1) * n * n].astype(np.float64), -1, 1)
+                    ref = orc.step(u0.reshape(n, n), n, md.delta, md.kernel, md.kernel_amp,
+                                   md.kernel_sigma, smp[k].c_F, md.beta1, md.tau)
+                    got = st[k * n * n:(k + 1) * n * n].astype(np.float64).reshape(n, n)
+                    assert np.max(np.abs(got - ref)) <= 1e-6, sh
+
+
+@pytest.mark.parametrize("n,R2", [(64, 4), (128, 64)])
+def test_autotuned_resident_layout(n, R2):
+    """AUTOTUNE times the resident layouts for the batch signature: results
+    within rounding of the default layout, and exactly repeatable once the
+    pick is cached."""
+    print("resident autotune n=%d R2=%d" % (n, R2), flush=True)
+    S = 512
+    md = _model(n, R2, 1)
+    host = np.random.default_rng(n + R2).uniform(-1, 1, S * n * n).astype(np.float32)
+    smp = [nlch.nlch_sample(0, 0, 1.0, md.kernel_amp, k * n * n) for k in range(S)]
+
+    def run(algo):
+        x = torch.from_numpy(host).to(DEV)
+        ooi = torch.zeros(2 * S, dtype=torch.float64, device=DEV)
+        nlch.nlch_solve_batch([md], smp, 40, nlch.NLCH_F32, algo, x, None, ooi)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), ooi.cpu().numpy()
+
+    d, od = run(nlch.NLCH_ALGO_RESIDENT)
+    t1, o1 = run(nlch.NLCH_ALGO_RESIDENT | nlch.NLCH_ALGO_AUTOTUNE)
+    t2, o2 = run(nlch.NLCH_ALGO_RESIDENT | nlch.NLCH_ALGO_AUTOTUNE)
+    assert np.array_equal(t1, t2) and np.array_equal(o1, o2)
+    assert np.max(np.abs(t1.astype(np.float64) - d)) <= 1e-4
+    assert np.max(np.abs(o1[1::2] - od[1::2])) <= 1e-6
