@@ -663,6 +663,11 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
             best = ms;
             pick = c;
         }
+        const char *verbose = std::getenv("NLCH_VERBOSE");
+        if (verbose && std::atoi(verbose) >= 2)
+            std::fprintf(stderr, "nlch autotune: n=%d R2=%d samples=%d candidate R=%d W=%d L=%d "
+                         "B=%d: %.4f ms per launch\n", g.n, g.R2, g.nids, c.R, c.W, c.L,
+                         stream_shape(g).B, ms / 3.0f);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -78,9 +78,13 @@ def test_kkt_conditions():
     assert np.all(np.abs(u) <= 1)
 
 
+@pytest.mark.parametrize("n", [10, 20, 32])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_newton_and_projected_gradient_agree(kind):
-    n, delta = 10, 2 / 10
+def test_newton_and_projected_gradient_agree(kind, n):
+    """The Newton step (z = xi u + mu) and accelerated projected gradient on
+    the box QP in u (dense A^-1; no shared reformulation) reach the same
+    point, up to 32^2 (1024 unknowns)."""
+    delta = 2 / 10 if n == 10 else 3 / n
     sigma = delta / 2
     amp = _amp_for(n, delta, kind, sigma, 0.1)
     u0 = _rand(n, 4 + kind)
@@ -105,14 +109,15 @@ def _amp_xi(n, delta, kind, sigma, xi):
     return _amp_for(n, delta, kind, sigma, xi)
 
 
-@pytest.mark.parametrize("xi", [-0.085, -0.01, 0.0])
+@pytest.mark.parametrize("n", [10, 20, 32])
+@pytest.mark.parametrize("xi", [-0.085, -0.01, -1e-12])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_split_step_active_set_and_projected_gradient_agree(kind, xi):
+def test_split_step_active_set_and_projected_gradient_agree(kind, xi, n):
     """For xi <= 0 (including the non-convex regime of the literal step,
     xi < -1/(tau lambda_max(A))) the split step is a strictly convex box QP:
     the active-set iteration and accelerated projected gradient reach the
-    same point."""
-    n, delta = 10, 2 / 10
+    same point, up to 32^2."""
+    delta = 2 / 10 if n == 10 else 3 / n
     sigma = delta / 2
     amp = _amp_xi(n, delta, kind, sigma, xi)
     u0 = _rand(n, 11 + kind)
