@@ -132,8 +132,10 @@ extern "C" {
                                     scratch), and the resident kernel's
                                     layouts (see nlch_set_resident_shape) on
                                     a copy of the states in a temporary
-                                    device buffer (min(nsteps, 10) steps);
-                                    keep the fastest (cached per process);
+                                    device buffer (min(nsteps, 10) steps;
+                                    the default layout unless another is 3%
+                                    faster); keep the fastest (cached per
+                                    process);
                                     synchronises hip_stream (the resident
                                     layouts are not tuned while hip_stream is
                                     being captured).  Shapes that split a band
