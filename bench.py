@@ -155,7 +155,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=512,
                     help="most samples the CPU oracle baseline may time")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="the CPU oracle baseline adds chunks of 16 samples until "
+                    help="the CPU oracle baseline adds chunks of up to 16 samples until "
                          "this much oracle time is spent")
     ap.add_argument("--fp64-samples", type=int, default=4)
     ap.add_argument("--resident-shape", default="0,0",
@@ -353,61 +353,80 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         o = ooi.view(-1, 2).cpu().numpy()
-        rel, tcpu, sscpu, k = [], 0.0, 0, 0
         cores = oracle.threads()
-        cap = min(args.cpu_samples, S)
-        chunk = 16
-        if any(mm.boundary for mm in w.models):
-            chunk = 4
-        if any(mm.beta2 > 0 for mm in w.models):
-            chunk = 1
-        # chunks of consecutive samples (all steps each) until the time
-        # budget is spent; the sample count is reported
-        while k < cap and tcpu < args.cpu_seconds:
-            idx = list(range(k, min(k + chunk, cap)))
-            by_model = {}
-            for i in idx:
-                by_model.setdefault(w.samples[i].model, []).append(i)
-            for mi, ids in by_model.items():
-                mm = w.models[mi]
-                u0 = np.stack([synth.initial_state(w, w.samples[i]).astype(ndt)
-                               .astype(np.float64) for i in ids])
-                t = time.perf_counter()
-                if mm.beta2 > 0:
-                    # the beta2 > 0 oracle (sparse direct Newton solves, one thread)
-                    from oracle import b2
-                    f1 = [b2.solve_b2(u0[j], w.nsteps, mm.n, mm.delta, mm.kernel,
-                                      w.samples[i].amp, mm.sigma, w.samples[i].c_F,
-                                      mm.beta1, mm.beta2, mm.tau)[2]
-                          for j, i in enumerate(ids)]
-                    cores = 1
-                elif mm.boundary:
-                    # the bounded-domain oracle (numpy, one thread)
-                    from oracle import volume
-                    f1 = [volume.solve(u0[j], w.nsteps, mm.n, mm.delta, mm.kernel,
-                                       w.samples[i].amp, mm.sigma, w.samples[i].c_F,
-                                       mm.beta1, mm.tau)[2] for j, i in enumerate(ids)]
-                    cores = 1
-                else:
-                    _, _, f1 = oracle.solve_many(u0, w.nsteps, mm.n, mm.delta, mm.kernel,
-                                                 mm.sigma, mm.beta1, mm.tau,
-                                                 [w.samples[i].c_F for i in ids],
-                                                 [w.samples[i].amp for i in ids],
-                                                 want_states=False)
-                tcpu += time.perf_counter() - t
-                sscpu += len(ids) * mm.n ** 2 * w.nsteps
-                for j, i in enumerate(ids):
-                    rel.append(abs(o[i, 1] - f1[j]) / abs(f1[j]))
-            k = idx[-1] + 1
+
+        def run_oracle(ids, nsteps):
+            """FP64 oracle outputs f1 of samples ids (all of one model) after
+            nsteps steps, and the threads it used."""
+            mm = w.models[w.samples[ids[0]].model]
+            u0 = np.stack([synth.initial_state(w, w.samples[i]).astype(ndt).astype(np.float64)
+                           for i in ids])
+            if mm.beta2 > 0:
+                # the beta2 > 0 oracle (sparse direct Newton solves, one thread)
+                from oracle import b2
+                return [b2.solve_b2(u0[j], nsteps, mm.n, mm.delta, mm.kernel, w.samples[i].amp,
+                                    mm.sigma, w.samples[i].c_F, mm.beta1, mm.beta2, mm.tau)[2]
+                        for j, i in enumerate(ids)], 1
+            if mm.boundary:
+                # the bounded-domain oracle (numpy, one thread)
+                from oracle import volume
+                return [volume.solve(u0[j], nsteps, mm.n, mm.delta, mm.kernel,
+                                     w.samples[i].amp, mm.sigma, w.samples[i].c_F, mm.beta1,
+                                     mm.tau)[2] for j, i in enumerate(ids)], 1
+            _, _, f1 = oracle.solve_many(u0, nsteps, mm.n, mm.delta, mm.kernel, mm.sigma,
+                                         mm.beta1, mm.tau, [w.samples[i].c_F for i in ids],
+                                         [w.samples[i].amp for i in ids], want_states=False)
+            return f1, cores
+
+        # one step of sample 0 first: its time decides how large a sample the
+        # budget allows
+        t = time.perf_counter()
+        _, cores = run_oracle([0], 1)
+        t1 = time.perf_counter() - t
+        n0 = w.models[w.samples[0].model].n
+        if t1 * w.nsteps > args.cpu_seconds:
+            # not even one whole sample fits: the first steps of sample 0
+            ksteps = max(1, min(w.nsteps, int(args.cpu_seconds / max(t1, 1e-9))))
+            t = time.perf_counter()
+            run_oracle([0], ksteps)
+            tcpu = time.perf_counter() - t
+            sscpu = n0 ** 2 * ksteps
+            sample = ("sample 0 of %d, its first %d of %d steps (%.1f s of oracle time)"
+                      % (S, ksteps, w.nsteps, tcpu))
+            rel, k = [], 0
+        else:
+            rel, tcpu, sscpu, k = [], 0.0, 0, 0
+            cap = min(args.cpu_samples, S)
+            # (the oracle spreads a chunk's samples over its threads, so a
+            # chunk of c samples takes about c / threads of c single runs)
+            chunk = int(max(1, min(16, args.cpu_seconds * cores / (2 * t1 * w.nsteps))))
+            # chunks of consecutive samples (all steps each) until the time
+            # budget is spent; the sample count is reported
+            while k < cap and tcpu < args.cpu_seconds:
+                idx = list(range(k, min(k + chunk, cap)))
+                by_model = {}
+                for i in idx:
+                    by_model.setdefault(w.samples[i].model, []).append(i)
+                for mi, ids in by_model.items():
+                    t = time.perf_counter()
+                    f1, cores = run_oracle(ids, w.nsteps)
+                    tcpu += time.perf_counter() - t
+                    sscpu += len(ids) * w.models[mi].n ** 2 * w.nsteps
+                    for j, i in enumerate(ids):
+                        rel.append(abs(o[i, 1] - f1[j]) / abs(f1[j]))
+                k = idx[-1] + 1
+            sample = ("samples 0..%d of %d, all %d steps each (%.1f s of oracle time)"
+                      % (k - 1, S, w.nsteps, tcpu))
         out["cpu_baseline"] = {"value": sscpu / tcpu, "unit": "site-steps/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": "samples 0..%d of %d, all %d steps each "
-                                         "(%.1f s of oracle time)"
-                                         % (k - 1, S, w.nsteps, tcpu),
+                               "cores": cores, "kind": "oracle", "sample": sample,
                                "host": host_info()}
-        out["ooi_rel_err"] = {"max": max(rel), "samples": k, "vs": "FP64 CPU oracle"}
-        log("cpu oracle %.3e site-steps/s on %d threads; max OoI rel err %.2e"
-            % (sscpu / tcpu, cores, max(rel)))
+        if rel:
+            out["ooi_rel_err"] = {"max": max(rel), "samples": k, "vs": "FP64 CPU oracle"}
+            log("cpu oracle %.3e site-steps/s on %d threads; max OoI rel err %.2e"
+                % (sscpu / tcpu, cores, max(rel)))
+        else:
+            out["ooi_rel_err"] = None  # no whole trajectory fits the CPU budget
+            log("cpu oracle %.3e site-steps/s on %d threads (%s)" % (sscpu / tcpu, cores, sample))
 
     print(json.dumps(out), flush=True)
 
