@@ -80,11 +80,13 @@ __device__ __forceinline__ double pdas_code(double u, double mu, double c) {
 
 // Stopping level of a split-step CG solve in the norm s.M^-1 s (M^-1 = d_act
 // on the active rows): the residual below 1e-14 max(1, |r'|), or, while the
-// active sets still change, reduced 1e4-fold.
+// active sets still change, reduced 10-fold (the sets, not the solve, are
+// what those iterations settle; the residual test after the sets repeat
+// still asks for the full accuracy).
 __device__ __forceinline__ double pdas_cg_stop(double rz0, double d_act, double scale,
                                                bool changed) {
     const double target = d_act * (1e-14 * scale) * (1e-14 * scale);
-    return changed ? fmax(1e-8 * rz0, target) : target;
+    return changed ? fmax(1e-2 * rz0, target) : target;
 }
 
 __device__ __forceinline__ double clampd(double v) {
