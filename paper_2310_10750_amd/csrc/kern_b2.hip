@@ -352,9 +352,9 @@ __global__ __launch_bounds__(kB2Threads) void k_b2_step(
         }
         if (it == kMaxNewton) break;
         // Jacobi-preconditioned conjugate gradients on J x = -F (x0 = 0),
-        // relative tolerance min(1e-2, |F| / scale) in the norm s.M^-1 s of
+        // relative tolerance min(0.1, |F| / scale) in the norm s.M^-1 s of
         // the residual (inexact Newton: superlinear near the root)
-        const double eta = fmin(1e-2, sqrt(f2) / scale);
+        const double eta = fmin(0.1, sqrt(f2) / scale);
         const double stop = eta * eta * f2r[1];
         double rz = f2r[1];
         for (int k = 0; k < kMaxCg && rz > stop; ++k) {
@@ -889,7 +889,7 @@ __global__ __launch_bounds__(THREADS) void k_b2_step_lds(
             if (valid(k)) Xl[site(k)] = 0.0f;  // a thread's own sites only
             Xlo[k] = 0.0f;
         }
-        const double eta = fmin(1e-2, sqrt(f2) / scale);
+        const double eta = fmin(0.1, sqrt(f2) / scale);
         const double stop = eta * eta * f2r[1];
         double rz = f2r[1];
         cg(mask, Sr, Xlo, rz, stop);
