@@ -127,7 +127,8 @@ extern "C" {
                                         synchronises hip_stream                 */
 #define NLCH_ALGO_AUTOTUNE 0x800 /* on the first call of a batch, time the
                                     streaming kernel's launch shapes (lanes'
-                                    columns, band height, waves per band) on
+                                    columns, band height, waves per band,
+                                    row phases per wave) on
                                     the caller's buffers (reads state, writes
                                     scratch), and the resident kernel's
                                     layouts (see nlch_set_resident_shape) on
@@ -139,7 +140,8 @@ extern "C" {
                                     synchronises hip_stream (the resident
                                     layouts are not tuned while hip_stream is
                                     being captured).  Shapes that split a band
-                                    over several waves, and resident layouts
+                                    over several waves or two row phases, and
+                                    resident layouts
                                     other than the default, sum some outputs
                                     in a different grouping: results can
                                     differ from the default by rounding only.
@@ -292,7 +294,7 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
  * 4 or 8), each of the first W-1 waves walking `periods` ring periods of
  * 2m+1 rows (W > 1), and band height B (W = 1); 0 keeps the default of a
  * field, and (0, 0, 0, 0) restores the default shape.  W > 1 applies to
- * groups with FP32 arithmetic and m <= 16 (others use W = 1); a group whose
+ * groups with FP32 arithmetic and m <= 32 (others use W = 1); a group whose
  * partial-sum areas for W waves would not fit in LDS uses fewer waves.
  * Results change with W > 1 by rounding only (see NLCH_ALGO_AUTOTUNE).
  * R = 4 (other fields 0) selects the tiled one-step kernel (32 x 32 output
@@ -302,6 +304,22 @@ int nlch_solve_batch_energy(const nlch_model *models, int32_t n_models,
  * where the streaming shape would give fewer than 1024 waves.
  * Host only; returns NLCH_EINVAL for values outside those ranges. */
 int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
+
+/* Row phases per wave of the streaming (ROWRUN) kernel for later
+ * nlch_solve_batch calls in this process, with the shape of
+ * nlch_set_stream_shape and overriding NLCH_ALGO_AUTOTUNE.  phases = 2
+ * (groups with FP32 arithmetic and W = 1): the two halves of each wave walk
+ * alternate rows of the band (even and odd input rows) over a strip of 32R
+ * columns, each forming the window sums of its own rows, and every output
+ * adds the partial sums of its two halves (one lane swap).  For a band
+ * height this gives twice the waves, so that bands can be twice as tall
+ * for the same parallelism and the 2m halo rows of a band (the disc rows
+ * above and below it, Sec. 2 eq. nonl_operator) weigh half as much.  Every
+ * disc sum is then formed in two parts, so results differ from phases = 1
+ * by rounding only.  phases = 1: one phase (the default shapes); 0: not
+ * forced (the default, or the autotuner's choice).  Host only; NLCH_EINVAL
+ * outside 0..2. */
+int nlch_set_stream_phases(int32_t phases);
 
 /* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
  * calls in this process, overriding the default and NLCH_ALGO_AUTOTUNE.
@@ -401,7 +419,7 @@ const char *nlch_last_error(void);
  * as usual.  NLCH_EINVAL for nth < 0. */
 int nlch_debug_inject_device_error(int32_t nth);
 
-/* ABI version: 5 (increments on any change to a struct, constant or function
+/* ABI version: 6 (increments on any change to a struct, constant or function
  * signature declared here). */
 int nlch_version(void);
 

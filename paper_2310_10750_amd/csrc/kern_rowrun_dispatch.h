@@ -25,20 +25,33 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // strip (R = 2 halves the window reads per site, R = 1 halves the register
 // ring); a band of B output rows is walked by W waves.  One wave per band
 // (k_stream) repeats the 2m halo rows of every band; W > 1 waves (k_band,
-// built for FP32 and m <= 16) share a band and hand partial sums over in LDS
-// instead.  Shapes with W = 1 give bit-identical results for every (R, B):
-// each site sums the same window sums in the same row order; with W > 1 the
-// sums of the outputs next to a hand-over point are formed in two parts,
+// built for FP32 and m <= 32) share a band and hand partial sums over in LDS
+// instead; PH = 2 (k_phase, FP32 arithmetic) lets the two halves of one wave
+// walk alternate rows of a band over a 32R-column strip.  Shapes with W = 1
+// and PH = 1 give bit-identical results for every (R, B): each site sums the
+// same window sums in the same row order; with W > 1 the sums of the outputs
+// next to a hand-over point, with PH = 2 every sum, are formed in two parts,
 // which changes their rounding only.
 template <int R2, int R, class TS, class TA, bool GAUSS>
 hipError_t stream_launch(const Group &g, const StreamShape &sh, const void *in, void *out,
                          hipStream_t s, double *epart) {
-    constexpr int TX = 64 * R;
     constexpr int P = Disc<R2>::P;
+    const int TX = 64 * R / sh.PH;
     const int strips = (g.ni + TX - 1) / TX;
     const int bands = (g.ni + sh.B - 1) / sh.B;
     const int64_t nb = (int64_t)strips * bands * g.nids;
-    if (nb > 0x7fffffff || sh.B < 1 || sh.W < 1 || sh.W > 8) return hipErrorInvalidValue;
+    if (nb > 0x7fffffff || sh.B < 1 || sh.W < 1 || sh.W > 8 || (sh.PH != 1 && sh.PH != 2))
+        return hipErrorInvalidValue;
+    if (sh.PH == 2) {
+        if constexpr (sizeof(TA) == 4) {
+            if (sh.W != 1) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_phase<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0,
+                               s, g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, sh.B, strips,
+                               bands, (int)nb, epart);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (sh.W == 1) {
         hipLaunchKernelGGL((k_stream<R2, R, TS, TA, GAUSS>), dim3((unsigned)nb), dim3(64), 0, s,
                            g.sd, g.ids, g.geo, (const TS *)in, (TS *)out, sh.B, strips, bands,

@@ -574,6 +574,199 @@ __global__ __launch_bounds__(512) void k_band(
 }
 
 // ---------------------------------------------------------------------------
+// Two-phase streaming step: one wave owns a strip of 32R columns and a band of
+// B output rows, and its two half-waves walk the band's input rows in
+// alternation (lanes 0-31 rows 0, 2, 4, ... of the B + 2m rows, lanes 32-63
+// rows 1, 3, 5, ...), each over the whole strip.  Every input row's window
+// sums are formed once, by the half that walks it, and each half keeps the
+// partial sums of its own rows for the outputs they feed; an output is the
+// sum of its two partial sums, exchanged by one lane swap
+// (v_permlane32_swap) when both are complete.  Against one wave per band
+// (k_stream) this gives twice the waves for a band height, so bands can be
+// twice as tall for the same number of waves and the 2m halo rows cost half
+// as much, with no hand-over through LDS.  Each output's disc sum is formed
+// in two parts (its even and its odd input rows), so results differ from
+// k_stream's by rounding only.
+//
+// Register ring.  Both halves run the same instructions, so a register names
+// a different output in each half: at iteration i half h walks input row
+// p = 2i + h and adds the window sum of disc row dy to slot
+// (2i - m - dy) mod S, which holds output q = slot + h (q relative to the
+// band's first row).  S = 2m + 2 slots hold every output a half can have
+// pending.  At iteration i the outputs 2i - 2m (finished by half 0) and
+// 2i - 2m + 1 (half 1) are complete: half 0 takes its own slot 2i - 2m and
+// half 1's slot 2i - 2m - 1, half 1 its own slot 2i - 2m and half 0's slot
+// 2i - 2m + 1; those slots are then cleared in the half that owned them.
+// ---------------------------------------------------------------------------
+template <int R2, int R, class TS, class TA, bool GAUSS>
+__global__ __launch_bounds__(64) void k_phase(
+    const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
+    const ModelGeo *__restrict__ geo, const TS *__restrict__ in,
+    TS *__restrict__ out, int B, int strips, int bands, int nblocks,
+    double *__restrict__ epart) {
+    constexpr int M = Disc<R2>::M;
+    constexpr int TX = 32 * R;            // strip columns
+    constexpr int TW = TX + 2 * M;        // staged row segment
+    constexpr int WIN = 2 * M + R;
+    constexpr int CPL = (TW + 31) / 32;   // staged elements per lane
+    // register ring slots (at least 2m + 2) and iterations per ring period;
+    // U is even, so that an iteration's parity is static in the unrolled
+    // loop and the prefetch buffers alternate without register moves
+    constexpr int U = (M + 2) & ~1;
+    constexpr int S = 2 * U;
+    constexpr int HS = 32 * CPL;          // ring elements per half-wave row
+    static_assert(sizeof(TA) == 4, "the lane swap moves 32-bit values");
+    // [row parity][half][element]; the ring holds the arithmetic type
+    __shared__ __align__(16) TA ring[2][2][HS];
+
+    const int n = geo->n;
+    const int lo = geo->lo, ne = n - geo->lo;  // updated block [lo, ne)^2
+    const int bidx = xcd_remap(blockIdx.x, nblocks);
+    const int per_sample = strips * bands;
+    const SampleDesc d = sd[ids[bidx / per_sample]];
+    const int t = bidx % per_sample;
+    const int x0 = lo + (t % strips) * TX;
+    const int y0 = lo + (t / strips) * B;
+    const TS *src = in + d.offset;
+    TS *dst = out + d.offset;
+    const int lane = threadIdx.x;
+    const int half = lane >> 5;
+    const int hl = lane & 31;
+    const int c0 = hl * R;
+    const int bq = y0 + B <= ne ? B : ne - y0;  // output rows of this band
+    const int iters = (bq + 2 * M + 1) / 2;     // input row pairs
+
+    // wrapped source columns of this lane's staged elements; lanes past the
+    // segment end re-read column 0 into the ring's padding
+    int gxs[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        int gx = (x0 - M + hl + 32 * k) % n;
+        gx += gx < 0 ? n : 0;
+        gxs[k] = hl + 32 * k < TW ? gx : 0;
+    }
+    // rows are fetched two iterations ahead into two buffers: iteration i
+    // stages pre[i & 1] and then loads the row of iteration i + 2 into it
+    // (gy is the last row fetched); a half's rows advance by two
+    int gy = (y0 - M + half) % n;
+    gy += gy < 0 ? n : 0;
+    TS pre[2][CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) pre[0][k] = src[(int64_t)gy * n + gxs[k]];
+    gy += 2;
+    gy -= gy >= n ? n : 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) pre[1][k] = src[(int64_t)gy * n + gxs[k]];
+
+    const TA ap = coef_ap<TA>(d), bcoef = coef_b<TA>(d), ce = geo_ce<TA>(geo);
+    TA g[M + 1];
+#pragma unroll
+    for (int k = 0; k <= M; ++k) g[k] = GAUSS ? geo_g<TA>(geo, k) : TA(1);
+
+    // centre values of the output this half finishes at iteration i, fetched
+    // two iterations ahead into cnext[i & 1] (row index clamped into the
+    // band: always a valid address)
+    int xcl[R];
+    TS cnext[2][R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int x = x0 + c0 + c;
+        xcl[c] = x < ne ? x : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        int q0 = 2 * e + half - 2 * M;
+        q0 = q0 < 0 ? 0 : (q0 < bq ? q0 : bq - 1);
+#pragma unroll
+        for (int c = 0; c < R; ++c) cnext[e][c] = src[(int64_t)(y0 + q0) * n + xcl[c]];
+    }
+
+    TA acc[S][R];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[i][c] = TA(-0.0);
+    TA e_ul = TA(0), e_pot = TA(0);
+
+    for (int ib = 0; ib < iters; ib += U) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int i = ib + j;
+            if (i < iters) {
+                TA *slot = ring[j & 1][half];  // ib is even (U is)
+                // this half finishes output q = 2i - 2m + half
+                const int q = 2 * i - 2 * M + half;
+                const int y = y0 + q;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) slot[hl + 32 * k] = to_acc<TA>(pre[j & 1][k]);
+                gy += 2;
+                gy -= gy >= n ? n : 0;
+                // unconditional (up to four rows past the band at the end;
+                // the row index wraps, so the address stays in the sample)
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) pre[j & 1][k] = src[(int64_t)gy * n + gxs[k]];
+                __syncthreads();  // one wave: makes the staged rows visible
+                TA win[WIN];
+                load_window<WIN, (R % 2 == 0)>(slot + c0, win);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    // a row past the band's last input row (odd row count)
+                    // feeds only outputs past the band, which are never
+                    // finished
+                    row_windows<R2, GAUSS>(win + c, g, [&](int dy) -> TA & {
+                        return acc[((2 * j - M - dy) % S + S) % S][c];
+                    });
+                }
+                // (static after unrolling)
+                const int own = ((2 * j - 2 * M) % S + S) % S;
+                const int sdn = (own + S - 1) % S;  // half 1's part of half 0's output
+                const int sup = (own + 1) % S;      // half 0's part of half 1's output
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const auto sw = __builtin_amdgcn_permlane32_swap(
+                        __float_as_uint(acc[sdn][c]), __float_as_uint(acc[sup][c]), false,
+                        false);
+                    const TA other = __uint_as_float(half ? sw[0] : sw[1]);
+                    const TA G = acc[own][c] + other;
+                    const int x = x0 + c0 + c;
+                    const TA u = to_acc<TA>(cnext[j & 1][c]);
+                    if (q >= 0 && q < bq && x < ne) {
+                        dst[(int64_t)y * n + x] = to_store<TS>(update_g<TA>(u, G, ap, bcoef));
+                        if (epart) {
+                            e_ul += u * lsum_of(ce, u, G);
+                            e_pot += TA(1) - u * u;
+                        }
+                    }
+                    acc[own][c] = TA(-0.0);
+                    acc[sdn][c] = half ? TA(-0.0) : acc[sdn][c];
+                    acc[sup][c] = half ? acc[sup][c] : TA(-0.0);
+                }
+                {
+                    // centre values of iteration i + 2
+                    int qn = q + 4;
+                    qn = qn < 0 ? 0 : (qn < bq ? qn : bq - 1);
+#pragma unroll
+                    for (int c = 0; c < R; ++c)
+                        cnext[j & 1][c] = src[(int64_t)(y0 + qn) * n + xcl[c]];
+                }
+            }
+        }
+    }
+    if (epart) {
+        // fixed shuffle tree: the partials do not depend on timing
+        double s_ul = (double)e_ul, s_pot = (double)e_pot;
+        for (int o = 32; o > 0; o >>= 1) {
+            s_ul += __shfl_xor(s_ul, o, 64);
+            s_pot += __shfl_xor(s_pot, o, 64);
+        }
+        if (lane == 0) {
+            epart[2 * (int64_t)bidx] = s_ul;
+            epart[2 * (int64_t)bidx + 1] = s_pot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS-resident multi-step kernel: one workgroup holds one whole n x n sample
 // in LDS (rows padded with an m-column periodic halo) and runs every step
 // without touching HBM.  Wave b owns the band of B rows starting at b*B

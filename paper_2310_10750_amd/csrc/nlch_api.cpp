@@ -589,9 +589,11 @@ struct TuneKey {
 };
 struct TuneVal {
     int R, B, W, L;
+    int PH;  // 2: two interleaved row phases per wave (W = 1)
 };
 std::map<TuneKey, TuneVal> g_tuned;
-TuneVal g_force{0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods)
+TuneVal g_force{0, 0, 0, 0, 0};  // nlch_set_stream_shape (L in ring periods),
+                                 // nlch_set_stream_phases
 int g_force_res_cols = 0;     // nlch_set_resident_shape
 int g_force_res_rows = 0;
 
@@ -603,10 +605,11 @@ void set_shape(Group &g, const TuneVal &v) {
     g.tune_B = v.B;
     g.tune_W = v.W;
     g.tune_L = v.L;
+    g.tune_PH = v.R == 4 ? 0 : v.PH;
     const bool built = tile_supported(g.ta_bytes == 8 ? kF64 : kF32, g.ta_bytes == 8, g.R2);
     if (v.R == 4) {
         g.tile = built;
-    } else if (v.R == 0 && v.W == 0 && v.B == 0) {
+    } else if (v.R == 0 && v.W == 0 && v.B == 0 && v.PH == 0) {
         const StreamShape sh = stream_shape(g);
         g.tile = built && (int64_t)sh.per_sample * g.nids < 1024;
     } else {
@@ -630,8 +633,19 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
         for (int B = bmin;; B *= 2) {
             const int Bc = B < g.ni ? B : g.ni;
             const int64_t waves = (int64_t)strips * ((g.ni + Bc - 1) / Bc) * g.nids;
-            if (waves >= 128 || Bc == bmin || Bc == g.ni) cands.push_back({R, Bc, 1, 0});
+            if (waves >= 128 || Bc == bmin || Bc == g.ni) cands.push_back({R, Bc, 1, 0, 0});
             if (Bc >= g.ni) break;
+        }
+        // two row phases per wave: strips of 32R columns, twice the waves;
+        // band heights bmin 2^k and 1.5 bmin 2^k
+        for (int B = bmin; g.ta_bytes == 4; B *= 2) {
+            for (int Bc : {B < g.ni ? B : g.ni, 3 * B / 2}) {
+                if (Bc > g.ni || (Bc != B && Bc == g.ni)) continue;
+                const int64_t waves =
+                    (int64_t)((g.ni + 32 * R - 1) / (32 * R)) * ((g.ni + Bc - 1) / Bc) * g.nids;
+                if (waves >= 128 || Bc == bmin || Bc == g.ni) cands.push_back({R, Bc, 1, 0, 2});
+            }
+            if (B >= g.ni) break;
         }
         if (R == 1 && tile_supported(prec, acc64, g.R2)) cands.push_back({4, 0, 0, 0});
         for (int W = 2; W <= 8 && band_built(g.m, g.ta_bytes); W *= 2)
@@ -645,7 +659,7 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    TuneVal pick{0, 0, 0, 0};
+    TuneVal pick{0, 0, 0, 0, 0};
     for (const TuneVal &c : cands) {
         set_shape(g, c);
         hipError_t e = launch_rowrun_step(prec, acc64, g, in, out, s);  // warm-up
@@ -666,8 +680,8 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
         const char *verbose = std::getenv("NLCH_VERBOSE");
         if (verbose && std::atoi(verbose) >= 2)
             std::fprintf(stderr, "nlch autotune: n=%d R2=%d samples=%d candidate R=%d W=%d L=%d "
-                         "B=%d: %.4f ms per launch\n", g.n, g.R2, g.nids, c.R, c.W, c.L,
-                         stream_shape(g).B, ms / 3.0f);
+                         "B=%d PH=%d: %.4f ms per launch\n", g.n, g.R2, g.nids, c.R, c.W, c.L,
+                         stream_shape(g).B, stream_shape(g).PH, ms / 3.0f);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -675,8 +689,8 @@ int autotune_group(Group &g, int dev, int prec, bool acc64, const void *in, void
     g_tuned[key] = pick;
     if (std::getenv("NLCH_VERBOSE"))
         std::fprintf(stderr, "nlch autotune: n=%d R2=%d samples=%d -> R=%d W=%d L=%d B=%d "
-                     "(%.3f ms per launch)\n", g.n, g.R2, g.nids, pick.R, pick.W, pick.L,
-                     stream_shape(g).B, best / 3.0f);
+                     "PH=%d (%.3f ms per launch)\n", g.n, g.R2, g.nids, pick.R, pick.W, pick.L,
+                     stream_shape(g).B, stream_shape(g).PH, best / 3.0f);
     return NLCH_OK;
 }
 
@@ -1023,13 +1037,13 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
             return fail(NLCH_EINVAL, "initial state holds %u non-finite values", *ctx->counter_h);
     }
 
-    if (g_force.R || g_force.W || g_force.L || g_force.B) {
+    if (g_force.R || g_force.W || g_force.L || g_force.B || g_force.PH) {
         // shape set by nlch_set_stream_shape (k periods per wave -> rows)
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
             if (b->variant[gi] != kRowrun) continue;
             Group &g = b->groups[gi];
             const int k = g_force.L > 0 ? g_force.L : 1;
-            set_shape(g, {g_force.R, g_force.B, g_force.W, k * (2 * g.m + 1)});
+            set_shape(g, {g_force.R, g_force.B, g_force.W, k * (2 * g.m + 1), g_force.PH});
         }
         b->tuned = false;
     } else if ((algo & NLCH_ALGO_AUTOTUNE) && !b->tuned) {
@@ -1084,6 +1098,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
         append_bytes(gk, g.tune_B);
         append_bytes(gk, g.tune_W);
         append_bytes(gk, g.tune_L);
+        append_bytes(gk, g.tune_PH);
         append_bytes(gk, g.res_cols);
         append_bytes(gk, g.res_rows);
         append_bytes(gk, g.tile);
@@ -1132,7 +1147,7 @@ static int solve_impl(const nlch_model *models, int32_t n_models, const nlch_sam
 
 extern "C" {
 
-int nlch_version(void) { return 5; }
+int nlch_version(void) { return 6; }
 
 const char *nlch_last_error(void) { return g_last_error.c_str(); }
 
@@ -1249,7 +1264,15 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B) {
         return fail(NLCH_EINVAL, "bad streaming shape (R in {0,1,2,4}, W in {0,1,2,4,8}, "
                                  "periods 0..64, B >= 0; R = 4 takes no other field)");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_force = {R, B, W, periods};
+    g_force = {R, B, W, periods, g_force.PH};
+    return NLCH_OK;
+}
+
+int nlch_set_stream_phases(int32_t phases) {
+    if (phases < 0 || phases > 2)
+        return fail(NLCH_EINVAL, "row phases per wave must be 0 (default), 1 or 2");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force.PH = phases;
     return NLCH_OK;
 }
 

@@ -75,6 +75,7 @@ struct Group {
     int32_t res_cols;        // resident kernel: columns per lane and rows each
     int32_t res_rows;        //   lane walks (0 = default)
     int32_t tile;            // row-run steps on 32 x 32 output tiles (k_tile)
+    int32_t tune_PH;         // 2: rows walked in two interleaved phases (k_phase)
     int32_t b2_newton;       // beta2 > 0 groups: samples with xi_h > 0 (Newton step)
     int32_t b2_split;        //   and with xi_h <= 0 (split step)
 };
@@ -106,9 +107,11 @@ inline int stream_lanes_cols(int n, int M, int nids) {
 
 // Launch shape of the streaming kernel: R columns per lane, W waves per
 // workgroup, band of B output rows; with W > 1 every wave but the last walks
-// L rows (a multiple of the ring period 2m+1) and B = W L - 2m.
+// L rows (a multiple of the ring period 2m+1) and B = W L - 2m.  PH = 2
+// (W = 1, FP32 arithmetic): the two half-waves walk alternate rows of the
+// band over a strip of 32R columns (k_phase).
 struct StreamShape {
-    int R, W, L, B, per_sample;
+    int R, W, L, B, per_sample, PH;
 };
 
 // LDS bytes of the streaming kernel: per wave a two-row staging ring of
@@ -135,6 +138,7 @@ inline StreamShape stream_shape(const Group &g) {
     StreamShape sh;
     sh.R = (g.tune_R == 1 || g.tune_R == 2) ? g.tune_R : stream_lanes_cols(g.ni, g.m, g.nids);
     sh.W = g.tune_W > 1 && band_built(g.m, g.ta_bytes) ? g.tune_W : 1;
+    sh.PH = sh.W == 1 && g.tune_PH == 2 && g.ta_bytes == 4 ? 2 : 1;
     // fewer waves per band where the partial-sum areas would not fit in LDS
     while (sh.W > 1 && stream_lds_bytes(sh.R, g.m, sh.W, g.ta_bytes) > 159 * 1024) sh.W /= 2;
     if (sh.W > 1) {
@@ -142,10 +146,12 @@ inline StreamShape stream_shape(const Group &g) {
         sh.B = sh.W * sh.L - 2 * g.m;
     } else {
         sh.L = 2 * g.m + 1;
-        sh.B = g.tune_B > 0 ? g.tune_B : stream_band_rows(g.ni, g.m, 64 * sh.R, g.nids);
+        sh.B = g.tune_B > 0 ? g.tune_B
+                            : stream_band_rows(g.ni, g.m, 64 * sh.R / sh.PH, g.nids);
     }
     if (sh.B > g.ni) sh.B = g.ni;
-    sh.per_sample = ((g.ni + 64 * sh.R - 1) / (64 * sh.R)) * ((g.ni + sh.B - 1) / sh.B);
+    const int tx = 64 * sh.R / sh.PH;  // strip columns
+    sh.per_sample = ((g.ni + tx - 1) / tx) * ((g.ni + sh.B - 1) / sh.B);
     return sh;
 }
 

@@ -117,6 +117,8 @@ def load():
     lib.nlch_solve_batch_energy.restype = ctypes.c_int
     lib.nlch_set_stream_shape.argtypes = [i32, i32, i32, i32]
     lib.nlch_set_stream_shape.restype = ctypes.c_int
+    lib.nlch_set_stream_phases.argtypes = [i32]
+    lib.nlch_set_stream_phases.restype = ctypes.c_int
     lib.nlch_set_resident_shape.argtypes = [i32, i32]
     lib.nlch_set_resident_shape.restype = ctypes.c_int
     lib.mfmc_estimate.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64,
@@ -254,6 +256,10 @@ def nlch_solve_batch_energy(models, samples, nsteps: int, precision: int, algo: 
 
 def nlch_set_stream_shape(R=0, W=0, periods=0, B=0) -> None:
     _check(load().nlch_set_stream_shape(R, W, periods, B))
+
+
+def nlch_set_stream_phases(phases=0) -> None:
+    _check(load().nlch_set_stream_phases(phases))
 
 
 def nlch_set_resident_shape(cols_per_lane=0, rows_per_lane=0) -> None:

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
             "nlch_version"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert nlch.nlch_version() == 5
+    assert nlch.nlch_version() == 6
 
 
 def test_struct_layouts_match_header():
@@ -264,3 +264,24 @@ def test_device_error_injection_switch():
         assert _err(nlch.nlch_debug_inject_device_error, -1) == nlch.NLCH_EINVAL
     finally:
         nlch.nlch_debug_inject_device_error(0)
+
+
+def test_launch_shape_calls_validate_their_arguments():
+    """The manual shape calls reject values outside their documented ranges
+    and accept (and reset) the valid ones, without a device."""
+    E = nlch.NLCH_EINVAL
+    try:
+        for bad in ((3, 1, 0, 0), (1, 3, 0, 0), (1, 2, 65, 0), (1, 1, 0, -1), (4, 2, 0, 0)):
+            assert _err(nlch.nlch_set_stream_shape, *bad) == E, bad
+        for bad in (-1, 3):
+            assert _err(nlch.nlch_set_stream_phases, bad) == E, bad
+        for bad in ((1, 4), (4, 32), (2, 8), (3, 16)):
+            assert _err(nlch.nlch_set_resident_shape, *bad) == E, bad
+        nlch.nlch_set_stream_shape(2, 1, 0, 256)
+        for ph in (0, 1, 2):
+            nlch.nlch_set_stream_phases(ph)
+        nlch.nlch_set_resident_shape(4, 8)
+    finally:
+        nlch.nlch_set_stream_shape(0, 0, 0, 0)
+        nlch.nlch_set_stream_phases(0)
+        nlch.nlch_set_resident_shape(0, 0)

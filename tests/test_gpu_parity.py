@@ -318,16 +318,17 @@ def reset_shape():
     nlch.nlch_set_stream_shape(0, 0, 0, 0)
 
 
-def test_single_wave_shapes_give_identical_results(reset_shape):
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_single_wave_shapes_give_identical_results(reset_shape, prec):
     """With one wave per band the launch shape (columns per lane, band
     height) does not change any result: every site sums the same window sums
-    in the same row order."""
-    w = _shape_workload()
+    in the same row order, with FP32 or FP16 storage."""
+    w = _shape_workload(prec)
     ref = DeviceBatch(w)
     ref.solve(nlch.NLCH_ALGO_ROWRUN)
     torch.cuda.synchronize()
     for R, B in ((1, 16), (2, 40), (1, 97), (2, 0), (1, 1024)):
-        print("shape R=%d W=1 B=%d" % (R, B), flush=True)
+        print("shape %s R=%d W=1 B=%d" % (prec, R, B), flush=True)
         nlch.nlch_set_stream_shape(R, 1, 0, B)
         b = DeviceBatch(w)
         b.solve(nlch.NLCH_ALGO_ROWRUN)
@@ -384,6 +385,76 @@ def test_multiwave_trajectory_and_repeatability(orc, reset_shape):
     b.solve(nlch.NLCH_ALGO_ROWRUN)
     torch.cuda.synchronize()
     assert torch.equal(a.state, b.state)
+    ref = oracle_samples(orc, w, [0, 3, 5], "f32")
+    o = a.ooi_host()
+    for i in (0, 3, 5):
+        assert abs(o[i, 1] - ref[i][2]) <= 1e-6 * abs(ref[i][2]), i
+        assert np.max(np.abs(a.sample_state(i) - ref[i][0])) <= 1e-4
+
+
+SHAPES_PH = [(1, 0), (2, 0), (1, 16), (2, 33), (1, 97), (2, 1024)]
+
+
+@pytest.fixture
+def reset_phases():
+    yield
+    nlch.nlch_set_stream_phases(0)
+    nlch.nlch_set_stream_shape(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("R,B", SHAPES_PH)
+def test_two_phase_bands_one_step(orc, reset_phases, R, B, prec):
+    """Two row phases per wave (the half-waves walk alternate input rows and
+    add each other's partial sums with a lane swap): one step from random
+    states against the oracle on every site, with odd and even band heights
+    (an odd count of input rows leaves the last one to one half), the
+    default height, bands taller than the lattice, ragged strips of 32R
+    columns and ragged bands (300^2, 130^2, 400^2), m = 8 to 32, both
+    kernels, and the energy trace on; FP64 groups keep one phase."""
+    w = _shape_workload(prec, nsteps=1, big=False)
+    print("two-phase R=%d B=%d %s" % (R, B, prec), flush=True)
+    nlch.nlch_set_stream_shape(R, 1, 0, B)
+    nlch.nlch_set_stream_phases(2)
+    b = DeviceBatch(w, prec)
+    rng = np.random.default_rng(6)
+    host = np.clip(rng.uniform(-1.5, 1.5, b.total), -1, 1).astype(NPD[prec])
+    b.state.copy_(torch.from_numpy(host).to(DEV))
+    b.init.copy_(b.state)
+    e = b.solve_energy(nlch.NLCH_ALGO_ROWRUN, nsteps=1)
+    torch.cuda.synchronize()
+    E = e.cpu().numpy()
+    for i, smp in enumerate(w.samples):
+        m = w.models[smp.model]
+        off = b.samples[i].offset
+        u0 = host[off:off + m.n * m.n].astype(np.float64).reshape(m.n, m.n)
+        ref = orc.step(u0, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F, m.beta1, m.tau)
+        got = b.sample_state(i)
+        assert np.max(np.abs(got - ref)) <= ONE_STEP_TOL[prec], (i, m.n)
+        e0 = orc.energy(u0, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F)
+        e1 = orc.energy(got, m.n, m.delta, m.kernel, smp.amp, m.sigma, smp.c_F)
+        etol = 1e-11 if prec == "f64" else 1e-5
+        assert abs(E[0, i] - e0) <= etol * abs(e0), (i, E[0, i], e0)
+        assert abs(E[1, i] - e1) <= etol * abs(e1), (i, E[1, i], e1)
+
+
+def test_two_phase_trajectory_and_repeatability(orc, reset_phases):
+    """Nine steps with two row phases per wave: the OoI stays within the FP32
+    trajectory bar of the oracle, the same shape repeats bit-exactly, and
+    the states stay within rounding of the one-phase shape."""
+    w = _shape_workload("f32", nsteps=9)
+    one = DeviceBatch(w)
+    one.solve(nlch.NLCH_ALGO_ROWRUN)
+    nlch.nlch_set_stream_shape(1, 1, 0, 64)
+    nlch.nlch_set_stream_phases(2)
+    a = DeviceBatch(w)
+    a.solve(nlch.NLCH_ALGO_ROWRUN)
+    b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_ROWRUN)
+    torch.cuda.synchronize()
+    assert torch.equal(a.state, b.state)
+    assert not torch.equal(a.state, one.state)  # the two-phase kernel ran
+    assert torch.max(torch.abs(a.state - one.state)).item() <= 1e-5
     ref = oracle_samples(orc, w, [0, 3, 5], "f32")
     o = a.ooi_host()
     for i in (0, 3, 5):
