@@ -89,6 +89,27 @@ def algorithmic_ops(m: int, kernel: int) -> int:
     return 2 * m + (2 * m + 1) + 5
 
 
+def split_window_ops(R2: int, C: int = 4) -> float:
+    """VALU lane-operations per site-step of k_resident4h on the constant
+    kernel, whose C columns per lane share running sums of their window: the
+    window win[0 .. 2m + C) is summed leftwards from its middle and
+    rightwards from it (2m + C - 2 additions per lane and row), and each
+    column's window sum of a half-width the disc uses is one addition of a
+    left and a right running sum when the window straddles the middle (else
+    a direct sum, 2w additions); then the 2m+1 disc-row additions and the 5
+    of the update, as in algorithmic_ops."""
+    m = math.isqrt(R2)
+    isqrt = math.isqrt
+    widths = sorted({isqrt(R2 - a * a) for a in range(m + 1)})
+    S = m + C // 2
+    per_lane = 2 * m + C - 2
+    for w in widths:
+        for c in range(C):
+            lo, hi = m + c - w, m + c + w
+            per_lane += 1 if (lo <= S - 1 and hi >= S) else 2 * w
+    return per_lane / C + (2 * m + 1) + 5
+
+
 def algorithmic_flops(m: int, kernel: int) -> int:
     """The same work in floating-point operations, a fused multiply-add
     counted as two and the projection's maximum and minimum as none: constant
@@ -255,11 +276,27 @@ def main():
     if resident and prec == "f32" and all(mm.n == 128 and not mm.boundary for mm in w.models) \
             and mdisc <= 8 and shape != (2, 16):
         kname = "k_resident4" if shape == (4, 16) else "k_resident4h"
+    # k_resident4h evaluates the constant kernel's windows (m >= 3) from
+    # running sums shared by a lane's four columns (fewer operations than
+    # 4m + 6)
+    def split(m, kernel):
+        return kname == "k_resident4h" and kernel == 0 and m >= 3
+
+    def ops_of(m, kernel, R2):
+        return split_window_ops(R2) if split(m, kernel) else algorithmic_ops(m, kernel)
+
+    def flops_of(m, kernel, R2):
+        # all window and row operations are additions; the update is 4 flops
+        return split_window_ops(R2) - 1 if split(m, kernel) else algorithmic_flops(m, kernel)
+
     def per_site(fn):
-        return sum(fn(nlch.nlch_disc(w.models[s.model].n, w.models[s.model].delta)[1],
-                      w.models[s.model].kernel) * w.models[s.model].n ** 2
-                   for s in w.samples) * w.nsteps
-    ops, flops = per_site(algorithmic_ops), per_site(algorithmic_flops)
+        tot = 0
+        for s in w.samples:
+            mm = w.models[s.model]
+            r2, md, _, _ = nlch.nlch_disc(mm.n, mm.delta)
+            tot += fn(md, mm.kernel, r2) * mm.n ** 2
+        return tot * w.nsteps
+    ops, flops = per_site(ops_of), per_site(flops_of)
     achieved = ops / (solve_ms * 1e-3) / 1e12
     tflops = flops / (solve_ms * 1e-3) / 1e12
     traffic = stored_traffic(kname, w.name)
@@ -271,8 +308,8 @@ def main():
                 "unit": "T lane-ops/s", "frac": round(achieved / peak_ops, 4),
                 "traffic": traffic, "kernel": kname,
                 "arithmetic": "f64" if f64 else "f32",
-                "ops_per_site_step": algorithmic_ops(mdisc, m0.kernel),
-                "flops_per_site_step": algorithmic_flops(mdisc, m0.kernel),
+                "ops_per_site_step": ops_of(mdisc, m0.kernel, R2),
+                "flops_per_site_step": flops_of(mdisc, m0.kernel, R2),
                 "achieved_tflops": round(tflops, 3), "peak_tflops": peak_tf,
                 "frac_flops": round(tflops / peak_tf, 4)}
     if not f64:

@@ -248,6 +248,55 @@ __global__ __launch_bounds__(256, 2) void k_resident4(
     }
 }
 
+// Window sums of one input row for the C adjacent columns of a lane at once,
+// constant kernel: the lane's window win[0 .. 2m + C) is split at
+// s = m + C/2 into running sums leftwards from s - 1 and rightwards from s,
+//     LS[j] = win[j] + ... + win[s - 1],   RS[j] = win[s] + ... + win[j],
+// so that a column's window of half-width w that straddles the split,
+// [m + c - w, m + c + w], sums to LS[m + c - w] + RS[m + c + w]: one addition
+// per column and half-width used by the disc, after 2m + C - 2 additions
+// shared by the C columns, instead of 2m per column.  Windows on one side of
+// the split (w = 0, and w = 1 next to it) are summed directly.  acc(dy, c)
+// names the accumulator of column c's output fed by disc row dy; each
+// receives the window sum of its row's half-width.  The running sums have at
+// most m + C/2 terms, like the window sums grown outwards from each column's
+// centre, so the rounding is of the same size; its grouping differs.  (For
+// m < 3 the shared sums cost as much as they save: not used there.)
+template <int R2, int C, class Acc>
+__device__ __forceinline__ void row_windows_split(const float *win, Acc &&acc) {
+    using D = Disc<R2>;
+    constexpr int M = D::M, S = M + C / 2, WIN = 2 * M + C;
+    float LS[S], RS[WIN];  // LS[j] for j < S, RS[j] for j >= S
+    LS[S - 1] = win[S - 1];
+#pragma unroll
+    for (int j = S - 2; j >= 0; --j) LS[j] = LS[j + 1] + win[j];
+    RS[S] = win[S];
+#pragma unroll
+    for (int j = S + 1; j < WIN; ++j) RS[j] = RS[j - 1] + win[j];
+    sfor<0, M + 1>([&](auto K) {
+        constexpr int w = K;
+        if constexpr (D::start[w] < D::start[w + 1]) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int lo = M + c - w, hi = M + c + w;
+                float H;
+                if (lo <= S - 1 && hi >= S) {
+                    H = LS[lo] + RS[hi];
+                } else {
+                    H = win[lo];
+#pragma unroll
+                    for (int j = lo + 1; j <= hi; ++j) H += win[j];
+                }
+                sfor<D::start[w], D::start[w + 1]>([&](auto E) {
+                    constexpr int dy = D::dy_by_w[E];
+                    float &r = acc(dy, c);
+                    r = r + H;
+                });
+            }
+        }
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Split-band variant (k_resident4h): four columns per lane as in
 // k_resident4, but one 16-row band per wave whose two half-waves walk 8
@@ -399,9 +448,15 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
                 win[4 * j + 2] = t.z;
                 win[4 * j + 3] = t.w;
             }
+            if constexpr (GAUSS || M < 3) {
 #pragma unroll
-            for (int c = 0; c < R; ++c) {
-                row_windows<R2, GAUSS>(win + c, g, [&](int dy) -> float & {
+                for (int c = 0; c < R; ++c) {
+                    row_windows<R2, GAUSS>(win + c, g, [&](int dy) -> float & {
+                        return acc[M + i - dy][c];
+                    });
+                }
+            } else {
+                row_windows_split<R2, R>(win, [&](int dy, int c) -> float & {
                     return acc[M + i - dy][c];
                 });
             }
