@@ -29,6 +29,18 @@ def test_algorithmic_flops(m):
     assert bench.algorithmic_flops(m, 1) == 7 * m + 6
 
 
+@pytest.mark.parametrize("R2,ops", [(9, 16.0), (16, 19.5), (25, 22.0), (64, 31.5)])
+def test_split_window_ops(R2, ops):
+    """Lane-ops per site-step of the four-column kernel's shared running
+    sums: at m = 8 the disc uses the half-widths 0, 3, 5, 6, 7, 8, so a
+    lane's row costs 2m + 2 = 18 running-sum additions plus 4 x 5 window
+    additions for its 4 columns (4.5 + 5 per site), then 2m + 1 = 17 row
+    additions and 5 for the update: 31.5 against the outward sums' 38."""
+    m = int(R2 ** 0.5)
+    assert bench.split_window_ops(R2) == ops
+    assert bench.split_window_ops(R2) < bench.algorithmic_ops(m, 0)
+
+
 def test_roofline_labels_in_source():
     """The roofline object names its unit in lane-operations, carries the
     FLOP-based fraction against the published 157.3 TFLOP/s, the LDS
