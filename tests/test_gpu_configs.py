@@ -27,14 +27,17 @@ def _check_all(b):
 
 
 def test_c3_full_batch_sampled_oracle(orc):
-    """4096 x 128^2, delta = 8h, 500 steps, FP32 (the benchmark workload)."""
+    """4096 x 128^2, delta = 8h, 500 steps, FP32 (the benchmark workload):
+    the OoI bar on 44 samples (their per-sample c_F spans the recipe's
+    range), enough to catch a systematic bias of the update that only some
+    samples' trajectories amplify past the bar."""
     print("C3 full", flush=True)
     w = synth.workload("C3")
     b = DeviceBatch(w)
     b.solve()
     torch.cuda.synchronize()
     _check_all(b)
-    idx = [0, 1, 2, 3, 1000, 2047, 3071, 4095]
+    idx = list(range(40)) + [1000, 2047, 3071, 4095]
     ref = oracle_samples(orc, w, idx, "f32")
     o = b.ooi_host()
     for i in idx:
