@@ -333,12 +333,12 @@ int nlch_set_stream_phases(int32_t phases);
  *            so that a CU's two resident samples give four waves per SIMD.
  *            Band sums are formed in two parts, so results differ from
  *            (2, 16) by FP32 rounding only.
- * 64^2 lattices (FP32 state, periodic domain): one column per lane, one band
- * of rows_per_lane rows per wave:
- *   (1, 8) (discs with m <= 8), (1, 16), (1, 32): 8, 4 or 2 waves per
- *            sample.  The partial sums a band hands to its neighbours group
- *            the disc rows differently, so results differ from (1, 16) by
- *            FP32 rounding only.
+ * 64^2 lattices (periodic domain): one column per lane, one band of
+ * rows_per_lane rows per wave:
+ *   (1, 8) (discs with m <= 8; FP32 or FP64 state), (1, 16), (1, 32) (FP32
+ *            state): 8, 4 or 2 waves per sample.  The partial sums a band
+ *            hands to its neighbours group the disc rows differently, so
+ *            results differ from (1, 16) by rounding only.
  * A shape applies to the groups of the lattice it names; other groups, and
  * cases a layout is not built for, keep their default.
  *   (0, 0):  the default: (4, 8) on 128^2 where built, else 16-row bands

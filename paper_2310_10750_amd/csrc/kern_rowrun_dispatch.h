@@ -90,13 +90,17 @@ hipError_t rowrun_launch(const Group &g, const void *in, void *out, hipStream_t 
 constexpr int kResB = 16;
 
 // Band height of a resident group: 16 rows, or for FP32 64^2 periodic
-// lattices the 8 or 32 rows that nlch_set_resident_shape or the autotuner
-// chose (m <= B: partial sums only reach the adjacent bands).
+// lattices the 8 or 32 rows, for FP64 ones the 8 rows, that
+// nlch_set_resident_shape or the autotuner chose (m <= B: partial sums only
+// reach the adjacent bands).
 template <class TS, class TA>
 int resident_band_rows(const Group &g, int M, bool vol) {
-    if (std::is_same<TS, float>::value && std::is_same<TA, float>::value && g.ni == 64 &&
-        !vol && (g.res_rows == 8 || g.res_rows == 32) && M <= g.res_rows)
+    if (g.ni != 64 || vol || M > g.res_rows) return kResB;
+    if (std::is_same<TS, float>::value && std::is_same<TA, float>::value &&
+        (g.res_rows == 8 || g.res_rows == 32))
         return g.res_rows;
+    if (std::is_same<TS, double>::value && std::is_same<TA, double>::value && g.res_rows == 8)
+        return 8;
     return kResB;
 }
 
@@ -140,6 +144,12 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
         if (g.ni == 64 && B == 32)
             return energy ? go(k_resident<R2, 64, 32, TS, TA, GAUSS, true, false>)
                           : go(k_resident<R2, 64, 32, TS, TA, GAUSS, false, false>);
+    }
+    if constexpr (std::is_same<TS, double>::value && std::is_same<TA, double>::value && M <= 8) {
+        // FP64 64^2 in 8-row bands: 8 waves for one sample (latency)
+        if (g.ni == 64 && B == 8)
+            return energy ? go(k_resident<R2, 64, 8, TS, TA, GAUSS, true, false>)
+                          : go(k_resident<R2, 64, 8, TS, TA, GAUSS, false, false>);
     }
     if (energy)
         return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, true, false>)

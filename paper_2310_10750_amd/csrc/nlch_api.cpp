@@ -731,6 +731,7 @@ int autotune_resident(Group &g, int dev, int prec, bool acc64, const nlch_sample
             cands.push_back({1, 32});
         }
     }
+    if (prec == kF64 && g.lo == 0 && g.ni == 64 && g.m <= 8) cands = {{1, 8}, {1, 16}};
     if (cands.empty() || nsteps < 1) return NLCH_OK;
     const TuneKey key{dev, prec, g.R2, g.kernel, g.n, g.lo, g.nids};
     auto it = g_tuned_res.find(key);

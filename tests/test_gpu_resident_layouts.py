@@ -146,6 +146,55 @@ def test_band_heights_of_the_64sq_resident_kernel(orc, R2, kind):
                     assert np.max(np.abs(got - ref)) <= 1e-6, sh
 
 
+def _solve64(md, smp, host, nsteps, shape):
+    nlch.nlch_set_resident_shape(*shape)
+    x = torch.from_numpy(host).to(DEV)
+    ooi = torch.zeros(2 * len(smp), dtype=torch.float64, device=DEV)
+    nlch.nlch_solve_batch([md], smp, nsteps, nlch.NLCH_F64, nlch.NLCH_ALGO_RESIDENT, x, None,
+                          ooi)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), ooi.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("R2", [1, 4, 9, 16, 25, 64])
+def test_fp64_band_heights_of_the_64sq_resident_kernel(orc, R2, kind):
+    """FP64 64^2 in 8-row bands (8 waves for a sample, the single-sample
+    latency case) against 16-row bands and the FP64 oracle at every site."""
+    print("64^2 FP64 band heights R2=%d kernel=%d" % (R2, kind), flush=True)
+    n, S = 64, 3
+    md = _model(n, R2, kind)
+    rng = np.random.default_rng(R2 * 11 + kind)
+    host = rng.uniform(-1.2, 1.2, S * n * n)
+    smp = [nlch.nlch_sample(0, 0, 0.97 + 0.02 * k, md.kernel_amp, k * n * n) for k in range(S)]
+    for nsteps in (1, 30):
+        s16, o16 = _solve64(md, smp, host, nsteps, (1, 16))
+        s8, o8 = _solve64(md, smp, host, nsteps, (1, 8))
+        assert np.max(np.abs(s8 - s16)) <= (1e-14 if nsteps == 1 else 1e-11)
+        np.testing.assert_allclose(o8, o16, rtol=1e-12, atol=1e-15)
+        if nsteps == 1:
+            for k in range(S):
+                u0 = np.clip(host[k * n * n:(k + 1) * n * n], -1, 1)
+                ref = orc.step(u0.reshape(n, n), n, md.delta, md.kernel, md.kernel_amp,
+                               md.kernel_sigma, smp[k].c_F, md.beta1, md.tau)
+                assert np.max(np.abs(s8[k * n * n:(k + 1) * n * n].reshape(n, n) - ref)) \
+                    <= 1e-13
+
+
+def test_fp64_single_sample_trajectory_in_8_row_bands(orc):
+    """The C1 recipe (one 64^2 sample, m = 4, 200 steps, FP64) in 8-row
+    bands: the OoI and every site against the FP64 oracle's trajectory."""
+    from tests.gpu_harness import oracle_samples
+    w = synth.workload("C1")
+    nlch.nlch_set_resident_shape(1, 8)
+    b = DeviceBatch(w)
+    b.solve(nlch.NLCH_ALGO_RESIDENT)
+    torch.cuda.synchronize()
+    ref = oracle_samples(orc, w, [0], "f64")[0]
+    assert abs(b.ooi_host()[0, 1] - ref[2]) <= 1e-12 * abs(ref[2])
+    assert np.max(np.abs(b.sample_state(0) - ref[0])) <= 1e-10
+
+
 @pytest.mark.parametrize("n,R2", [(64, 4), (128, 64)])
 def test_autotuned_resident_layout(n, R2):
     """AUTOTUNE times the resident layouts for the batch signature: results
