@@ -316,9 +316,9 @@ int nlch_set_stream_shape(int32_t R, int32_t W, int32_t periods, int32_t B);
  * for the same parallelism and the 2m halo rows of a band (the disc rows
  * above and below it, Sec. 2 eq. nonl_operator) weigh half as much.  Every
  * disc sum is then formed in two parts, so results differ from phases = 1
- * by rounding only.  phases = 1: one phase (the default shapes); 0: not
- * forced (the default, or the autotuner's choice).  Host only; NLCH_EINVAL
- * outside 0..2. */
+ * by rounding only.  phases = 1: one phase (one wave or W waves per band;
+ * the tiled kernel is then not used); 0: not forced (the default, or the
+ * autotuner's choice).  Host only; NLCH_EINVAL outside 0..2. */
 int nlch_set_stream_phases(int32_t phases);
 
 /* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
