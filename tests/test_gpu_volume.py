@@ -135,22 +135,26 @@ def test_volume_trajectory(orc, n, R2, kind, prec, algo):
         assert abs(o[i, 0] - own) <= 1e-12
 
 
-@pytest.mark.parametrize("shape", [(2, 1, 0, 0), (1, 2, 1, 0), (2, 4, 2, 0), (1, 8, 1, 0),
-                                   (1, 1, 0, 40)])
+@pytest.mark.parametrize("shape", [(2, 1, 0, 0, 0), (1, 2, 1, 0, 0), (2, 4, 2, 0, 0),
+                                   (1, 8, 1, 0, 0), (1, 1, 0, 40, 0), (1, 1, 0, 0, 2),
+                                   (2, 1, 0, 37, 2)])
 def test_volume_stream_shapes(orc, shape):
     """Forced launch shapes of the streaming kernels (columns per lane, waves
-    per band, periods, band rows) on the bounded domain, FP32, m = 8 and a
-    ragged 150-node lattice: one step against the oracle at every node."""
-    R, W, k, B = shape
-    print("volume shape R=%d W=%d k=%d B=%d" % shape, flush=True)
+    per band, periods, band rows, row phases per wave) on the bounded domain,
+    FP32, m = 8 and a ragged 150-node lattice: one step against the oracle at
+    every node."""
+    R, W, k, B, ph = shape
+    print("volume shape R=%d W=%d k=%d B=%d phases=%d" % shape, flush=True)
     w, m = _workload(150, 64, 1, "f32", S=2, nsteps=1)
     nlch.nlch_set_stream_shape(R, W, k, B)
+    nlch.nlch_set_stream_phases(ph)
     try:
         b = DeviceBatch(w, "f32")
         b.solve(nlch.NLCH_ALGO_ROWRUN)
         torch.cuda.synchronize()
     finally:
         nlch.nlch_set_stream_shape(0, 0, 0, 0)
+        nlch.nlch_set_stream_phases(0)
     side = synth.state_side(m)
     for i, s in enumerate(w.samples):
         off = b.samples[i].offset
