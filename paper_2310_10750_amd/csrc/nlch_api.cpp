@@ -926,12 +926,56 @@ int enqueue_solve(Batch &b, DevCtx &ctx, int prec, bool acc64, int nsteps, void 
         }
     }
     // group 0 (the first model, the high-fidelity level in an MFMC batch) on
-    // the caller's stream, the rest round-robin on the auxiliary streams
-    for (size_t gi = 0; gi < G && !rc; ++gi) {
-        hipStream_t sg = gi == 0 ? s : ctx.aux[(gi - 1) % naux];
-        rc = enqueue_group(b, gi, prec, acc64, nsteps, state, scratch, ooi, energy, estride,
-                           sg);
-    }
+    // the caller's stream, the rest round-robin on the auxiliary streams.
+    // The launches are enqueued step-major (step k of every streaming group,
+    // then step k + 1), not group by group: the runtime keeps only a few
+    // launches in flight ahead of the device, so a group-major order would
+    // hold the later groups back until the host had nearly finished enqueuing
+    // the first group's chain, and the levels would hardly overlap.
+    if (!rc) rc = [&]() -> int {
+        struct Run {
+            size_t gi;
+            hipStream_t s;
+            void *cur, *nxt;
+            double *ep;
+            int ps;
+        };
+        std::vector<Run> runs;
+        for (size_t gi = 0; gi < G; ++gi) {
+            hipStream_t sg = gi == 0 ? s : ctx.aux[(gi - 1) % naux];
+            const Group &g = b.groups[gi];
+            if (b.variant[gi] == kResident) {
+                HIP_TRY(launch_resident(prec, acc64, g, state, nsteps, ooi, sg, energy, estride));
+                continue;
+            }
+            // as enqueue_group: the steps ping-pong so that the last lands in
+            // state; under a volume constraint both buffers get the ring
+            void *buf0 = (nsteps % 2) ? scratch : state;
+            void *buf1 = (buf0 == state) ? scratch : state;
+            if (g.lo != 0 && nsteps > 0) HIP_TRY(launch_project(prec, g, state, buf1, sg));
+            HIP_TRY(launch_project(prec, g, state, buf0, sg));
+            runs.push_back({gi, sg, buf0, buf1, energy ? group_epart(b, gi) : nullptr,
+                            step_blocks_per_sample(b.variant[gi], g)});
+        }
+        for (int k = 0; k <= nsteps; ++k) {
+            if (k == nsteps && !energy) break;
+            for (Run &r : runs) {
+                const Group &g = b.groups[r.gi];
+                if (k == nsteps) {
+                    r.cur = state;
+                    r.nxt = scratch;
+                }
+                HIP_TRY(launch_step(b.variant[r.gi], prec, acc64, g, r.cur, r.nxt, r.s, r.ep,
+                                    k > 0));
+                if (energy)
+                    HIP_TRY(launch_energy_final(g, r.ep, r.ps, energy + (int64_t)k * estride,
+                                                r.s));
+                std::swap(r.cur, r.nxt);
+            }
+        }
+        for (const Run &r : runs) HIP_TRY(launch_ooi(prec, b.groups[r.gi], state, ooi, 2, r.s));
+        return NLCH_OK;
+    }();
     // Join every forked stream back into s, after a failure too: a capture
     // must end joined, and later work on s must follow what the auxiliary
     // streams already hold.  (Not subject to failure injection.)
