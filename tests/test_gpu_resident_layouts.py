@@ -146,6 +146,30 @@ def test_band_heights_of_the_64sq_resident_kernel(orc, R2, kind):
                     assert np.max(np.abs(got - ref)) <= 1e-6, sh
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_default_layout_invariants_bit_exact(kind):
+    """The default 128^2 FP32 layout (four columns per lane, split bands;
+    for the constant kernel the windows come from running sums shared by a
+    lane's four columns): the step commutes with negation, keeps u = 1, -1
+    and 0 fixed, and commutes with translations by whole bands (16 rows) and
+    whole four-column groups, all bit for bit, over three steps."""
+    n, S, nsteps = 128, 1, 3
+    md = _model(n, 64, kind)
+    smp = [nlch.nlch_sample(0, 0, 0.98, md.kernel_amp, 0)]
+    rng = np.random.default_rng(40 + kind)
+    u = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+    base, _ = _solve(md, smp, u.reshape(-1), nsteps, (0, 0))
+    base = base.reshape(n, n)
+    neg, _ = _solve(md, smp, (-u).reshape(-1), nsteps, (0, 0))
+    assert np.array_equal(neg.reshape(n, n), -base)
+    for c in (1.0, -1.0, 0.0):
+        st, _ = _solve(md, smp, np.full(n * n, c, dtype=np.float32), nsteps, (0, 0))
+        assert np.array_equal(st, np.full(n * n, c, dtype=np.float32)), c
+    for sh in ((16, 0), (0, 4), (32, 8), (48, 124)):
+        st, _ = _solve(md, smp, np.roll(u, sh, (0, 1)).reshape(-1), nsteps, (0, 0))
+        assert np.array_equal(st.reshape(n, n), np.roll(base, sh, (0, 1))), sh
+
+
 def _solve64(md, smp, host, nsteps, shape):
     nlch.nlch_set_resident_shape(*shape)
     x = torch.from_numpy(host).to(DEV)
