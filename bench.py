@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -67,15 +68,24 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text: str) -> str:
+    """A C++ source without its comments, trailing blanks and blank lines
+    (the kernel sources hold no comment markers inside string literals)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def kernel_source_hash(kernel="k_resident"):
     """Hash of a kernel's sources, to tell whether stored counter data still
-    describe the current kernel."""
+    describe the current kernel.  Comments do not count: a change to them
+    alone leaves the compiled kernel as it was."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2310_10750_amd", "csrc")
     for f in KERNEL_SOURCES.get(kernel, sorted(os.listdir(csrc))):
         h.update(f.encode())
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -273,9 +283,15 @@ def main():
         (args.algo & 0xff) in (0, 3)
     kname = "k_resident" if resident else "k_rowrun"
     shape = tuple(int(v) for v in args.resident_shape.split(","))
-    if resident and prec == "f32" and all(mm.n == 128 and not mm.boundary for mm in w.models) \
-            and mdisc <= 8 and shape != (2, 16):
-        kname = "k_resident4" if shape == (4, 16) else "k_resident4h"
+    # FP32 128^2 (periodic, or Omega inside its ring): four columns per lane
+    # in split bands by default; (4, 16) is built for the periodic lattice
+    # only (a bounded domain then runs the two-column kernel)
+    boundary = any(mm.boundary for mm in w.models)
+    if resident and prec == "f32" and all(mm.n == 128 for mm in w.models) and mdisc <= 8:
+        if shape == (4, 16):
+            kname = "k_resident" if boundary else "k_resident4"
+        elif shape != (2, 16):
+            kname = "k_resident4h"
     # k_resident4h evaluates the constant kernel's windows (m >= 3) from
     # running sums shared by a lane's four columns (fewer operations than
     # 4m + 6)

@@ -321,11 +321,23 @@ __device__ __forceinline__ void row_windows_split(const float *win, Acc &&acc) {
 // neighbouring band (above for half 0, below for half 1), acc[m..H+m) the
 // half's own rows, and acc[H+m..H+2m) the sums for the other half's rows,
 // which arrive by one lane swap (v_permlane32_swap) per value.  The sums for
-// the neighbouring bands are handed over in place as in k_resident4.  Each
-// band sum is formed in two parts, so states differ from k_resident4's by
-// FP32 rounding only.
+// the neighbouring bands are handed over in place, in the half's own rows
+// (their values are back in registers by then).
+// Each band sum is formed in two parts, so states differ from k_resident4's
+// by FP32 rounding only.
+//
+// Volume constraint (VOL): Omega's 128 x 128 lattice inside a ring of m fixed
+// rows and columns, stored (128 + 2m)^2.  The ring columns of Omega's rows
+// fill the LDS halo once for the whole solve (the halo holds the periodic
+// copies otherwise); the window sums of the m ring rows above and below are
+// formed once into two blocks after the state rows, which Omega's first and
+// last half-bands receive every step in place of a neighbour's hand-over.
+// The hand-over then goes into the Omega columns of the half's rows (row
+// stride n + 2m), so the ring columns are never overwritten; the periodic
+// kernel packs it contiguously (row stride n) over a halo that the next
+// publish rewrites anyway.
 // ---------------------------------------------------------------------------
-template <int R2, bool GAUSS, bool ENERGY>
+template <int R2, bool GAUSS, bool ENERGY, bool VOL>
 __global__ __launch_bounds__(512, 4) void k_resident4h(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, float *__restrict__ state, int nsteps,
@@ -338,10 +350,26 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
     constexpr int NB = N / B;
     static_assert(M <= H && M * N <= H * TW, "partial sums must fit in the half-band's rows");
     static_assert(TW % 4 == 0 && 4 * 31 + 4 * WIN4 <= TW, "aligned windows");
+    static_assert(!(VOL && ENERGY), "no energy trace under a volume constraint");
+    // the stored array: Omega (N x N) inside a ring of m fixed rows and
+    // columns under a volume constraint, else the periodic lattice itself
+    constexpr int S = VOL ? N + 2 * M : N;
+    constexpr int OFF = VOL ? M : 0;
+    static_assert(!VOL || S <= TW, "the ring columns sit in the LDS halo");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[8];
 
     float *lds = reinterpret_cast<float *>(smem_raw);
+    // Under a volume constraint the LDS holds, after the state rows, the fixed
+    // sums of the m ring rows above and below Omega (m rows of N each), and
+    // no static area (two samples per CU fill the LDS): the final reduction
+    // then uses the start of the state rows, which the solve no longer needs.
+    double *red;
+    if constexpr (VOL) {
+        red = reinterpret_cast<double *>(smem_raw);
+    } else {
+        __shared__ double red_s[8];
+        red = red_s;
+    }
     const int sidx = ids[blockIdx.x];
     const SampleDesc d = sd[sidx];
     float *g_state = state + d.offset;
@@ -357,10 +385,20 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
     const int rstep = half ? -1 : 1;
     const int bup = band + 1 < NB ? band + 1 : 0;  // the band below
     const int bdn = band > 0 ? band - 1 : NB - 1;  // the band above
-    // sums this half receives: the band above's half 1 (for half 0), the
-    // band below's half 0 (for half 1), each in that half's own rows
-    const float *recv = lds + (half ? bup * B : bdn * B + H) * TW;
+    // Sums this half receives: the band above's half 1 (for half 0), the
+    // band below's half 0 (for half 1), each handed over in that half's own
+    // rows (LDS rows from rrow).  Under a volume constraint the hand-over goes
+    // through the Omega columns of those rows (LDS row rrow + j holds slot j;
+    // the halo keeps the fixed ring columns), and Omega's first half-band
+    // instead receives the fixed sums of the ring rows above it, its last
+    // those of the ring rows below (blocks of m rows of N).
+    const int rrow = half ? bup * B : bdn * B + H;
+    const bool edge = VOL && ((band == 0 && !half) || (band == NB - 1 && half));
+    const float *blk = lds + N * TW + (half ? M * N : 0);
+    // periodic lattice: the hand-over blocks are m rows of N values from the
+    // start of a half's rows (contiguous; the halo is rewritten every step)
     float *mine = lds + yh * TW;
+    const float *recv = lds + rrow * TW;
 
     const float ap = coef_ap<float>(d), bcoef = coef_b<float>(d), ce = geo_ce<float>(geo);
     float g[M + 1];
@@ -396,23 +434,106 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
     float st[H][R];
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-        const float4 t = *reinterpret_cast<const float4 *>(
-            g_state + (int64_t)(rbase + k * rstep) * N + xb);
-        st[k][0] = clamp1(t.x);
-        st[k][1] = clamp1(t.y);
-        st[k][2] = clamp1(t.z);
-        st[k][3] = clamp1(t.w);
+        const float *gp = g_state + (int64_t)(rbase + k * rstep + OFF) * S + xb + OFF;
+        if constexpr (OFF % 4 == 0) {
+            const float4 t = *reinterpret_cast<const float4 *>(gp);
+            st[k][0] = clamp1(t.x);
+            st[k][1] = clamp1(t.y);
+            st[k][2] = clamp1(t.z);
+            st[k][3] = clamp1(t.w);
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) st[k][c] = clamp1(gp[c]);
+        }
+    }
+
+    if constexpr (VOL) {
+        // The ring columns of this half's rows, projected, into the LDS halo
+        // for the whole solve (and back to HBM); LDS column = stored column.
+        for (int t = lane & 31; t < H * 2 * M; t += 32) {
+            const int k = t / (2 * M), j = t - k * 2 * M;
+            const int col = j < M ? j : N + j;
+            float *gp = g_state + (int64_t)(rbase + k * rstep + M) * S + col;
+            const float v = clamp1(*gp);
+            lds[(yh + k) * TW + col] = v;
+            *gp = v;
+        }
+        // The window sums of the ring rows, accumulated into the outputs of
+        // Omega's first and last m rows (band 0: half 0 the ring above, half
+        // 1 the ring below).  Half 1 walks the ring below from the bottom
+        // up, and by the symmetry of the disc (row dy and row -dy have the
+        // same half-width and weight) its register at[q] then collects
+        // Omega row N - 1 - q, as half 0's collects row q: both halves run
+        // the same code.  Stored as the hand-over blocks their receivers
+        // read: slot j holds Omega row m - 1 - j (above) or N - m + j (below),
+        // both at[m - 1 - j].
+        if (band == 0) {
+            float at[M][R];
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int c = 0; c < R; ++c) at[q][c] = -0.0f;
+            sfor<0, M>([&](auto I) {
+                constexpr int i = I;
+                // stored row of ring row i: above Omega (Omega row i - m) or
+                // below it (Omega row N + m - 1 - i)
+                float *gp = g_state + (int64_t)(half ? N + 2 * M - 1 - i : i) * S + xb;
+                float win[2 * M + R];
+#pragma unroll
+                for (int t = 0; t < 2 * M + R; ++t) win[t] = clamp1(gp[t]);
+                // the projected ring rows back to HBM (the lanes' windows
+                // overlap: lanes storing the same element store the same value)
+#pragma unroll
+                for (int t = 0; t < 2 * M + R; ++t) gp[t] = win[t];
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    float sink = 0.0f;
+                    row_windows<R2, GAUSS>(win + c, g, [&](int dy) -> float & {
+                        const int q = i - M - dy;  // output fed by disc row dy
+                        return (q >= 0 && q < M) ? at[q][c] : sink;
+                    });
+                }
+            });
+            float *blk = lds + N * TW + (half ? M * N : 0);
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                *reinterpret_cast<float4 *>(blk + j * N + xb) =
+                    make_float4(at[M - 1 - j][0], at[M - 1 - j][1], at[M - 1 - j][2],
+                                at[M - 1 - j][3]);
+        }
     }
 
     // With the energy trace one more pass evaluates E_h(u^nsteps) and keeps
     // the state.
     const int passes = nsteps + (ENERGY ? 1 : 0);
     for (int step = 0; step < passes; ++step) {
-        // Publish this half's rows; the lanes at the lattice edge then write
-        // the periodic column halo in stores of their own.
+        // Publish this half's rows; then the periodic column halo.  (Under a
+        // volume constraint the halo holds the fixed ring columns.)
 #pragma unroll
         for (int k = 0; k < H; ++k) put4((yh + k) * TW + M + xb, st[k]);
-        if (xb < M || xb + 4 > N - M) {
+        if constexpr (!VOL && M % 4 == 0) {
+            // The halo of the half's H rows is H * m/2 chunks of 4 values
+            // (32 for m = 8): each lane copies at most one chunk from the
+            // published row, one read and one write, instead of the edge
+            // lanes' H stores that every lane would issue.  Chunk q of row k:
+            // q < m/4 the left halo (LDS columns 4q.., copies of Omega columns
+            // N - m + 4q..), else the right halo (LDS columns m + N + 4q'..,
+            // copies of Omega columns 4q'.., q' = q - m/4).
+            constexpr int QC = M / 2;
+            static_assert(H * QC <= 32, "one chunk per lane of the half-wave");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int hl = lane & 31;
+            if (hl < H * QC) {
+                const int k = hl / QC, q = hl - k * QC;
+                const int left = q < QC / 2;
+                const int dst = left ? 4 * q : M + N + 4 * (q - QC / 2);
+                const int src = left ? N + 4 * q : M + 4 * (q - QC / 2);
+                const float4 t = *reinterpret_cast<const float4 *>(lds + (yh + k) * TW + src);
+                *reinterpret_cast<float4 *>(lds + (yh + k) * TW + dst) = t;
+            }
+        } else if (!VOL && (xb < M || xb + 4 > N - M)) {
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 const int x = xb + c;
@@ -485,19 +606,35 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-            *reinterpret_cast<float4 *>(mine + j * N + xb) =
-                make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+        for (int j = 0; j < M; ++j) {
+            if constexpr (VOL) {
+                const float v[4] = {acc[j][0], acc[j][1], acc[j][2], acc[j][3]};
+                put4((yh + j) * TW + M + xb, v);
+            } else {
+                *reinterpret_cast<float4 *>(mine + j * N + xb) =
+                    make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+            }
+        }
         __syncthreads();
         // slot j of the neighbour's half is its acc[j]: output row m - 1 - j
         // of that half's walk direction, this half's acc[2m - 1 - j]
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const float4 t = *reinterpret_cast<const float4 *>(recv + j * N + xb);
-            acc[2 * M - 1 - j][0] += t.x;
-            acc[2 * M - 1 - j][1] += t.y;
-            acc[2 * M - 1 - j][2] += t.z;
-            acc[2 * M - 1 - j][3] += t.w;
+            float v[4];
+            if (VOL && !edge) {
+                get4((rrow + j) * TW + M + xb, v);
+            } else {
+                const float4 t =
+                    *reinterpret_cast<const float4 *>((VOL ? blk : recv) + j * N + xb);
+                v[0] = t.x;
+                v[1] = t.y;
+                v[2] = t.z;
+                v[3] = t.w;
+            }
+            acc[2 * M - 1 - j][0] += v[0];
+            acc[2 * M - 1 - j][1] += v[1];
+            acc[2 * M - 1 - j][2] += v[2];
+            acc[2 * M - 1 - j][3] += v[3];
         }
         // the neighbours have read this half's rows before it publishes the
         // next state there
@@ -535,8 +672,13 @@ __global__ __launch_bounds__(512, 4) void k_resident4h(
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-        *reinterpret_cast<float4 *>(g_state + (int64_t)(rb + k * rs) * N + xw) =
-            make_float4(st[k][0], st[k][1], st[k][2], st[k][3]);
+        float *gp = g_state + (int64_t)(rb + k * rs + OFF) * S + xw + OFF;
+        if constexpr (OFF % 4 == 0) {
+            *reinterpret_cast<float4 *>(gp) = make_float4(st[k][0], st[k][1], st[k][2], st[k][3]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) gp[c] = st[k][c];
+        }
 #pragma unroll
         for (int c = 0; c < R; ++c) part += (double)st[k][c];
     }
@@ -564,12 +706,19 @@ static hipError_t resident4_go(const Group &g, void *state, int nsteps, double *
     constexpr int M = Disc<R2>::M;
     if constexpr (resident4_fits(128, M, 16)) {
         constexpr size_t kLds = 160 * 1024;
-        const size_t lds4 = resident4_lds_bytes(128, M);
+        // a volume constraint: Omega (128^2) inside a ring of m, split bands,
+        // the ring rows' fixed sums after the state rows
+        const bool vol = g.lo != 0;
+        const size_t lds4 =
+            resident4_lds_bytes(128, M) + (vol ? (size_t)2 * M * 128 * sizeof(float) : 0);
         // rows per lane: 8 (split bands, 8 waves) unless 16 are asked for
-        const bool split = g.res_rows != 16;
-        auto f = split ? (energy ? k_resident4h<R2, GAUSS, true> : k_resident4h<R2, GAUSS, false>)
-                       : (energy ? k_resident4<R2, GAUSS, true> : k_resident4<R2, GAUSS, false>);
-        if (g.ni != 128 || g.lo != 0 || lds4 > kLds - 1024 ||
+        const bool split = vol || g.res_rows != 16;
+        auto f = vol ? k_resident4h<R2, GAUSS, false, true>
+                     : split ? (energy ? k_resident4h<R2, GAUSS, true, false>
+                                       : k_resident4h<R2, GAUSS, false, false>)
+                             : (energy ? k_resident4<R2, GAUSS, true> : k_resident4<R2, GAUSS, false>);
+        if (g.ni != 128 || (vol && (g.lo != M || energy || g.n != 128 + 2 * M)) ||
+            lds4 > kLds - 1024 ||
             (lds4 > 64 * 1024 &&
              hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)(kLds - 1024)) != hipSuccess))

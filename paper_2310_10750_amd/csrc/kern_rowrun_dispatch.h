@@ -127,9 +127,16 @@ hipError_t resident_launch(const Group &g, void *state, int nsteps, double *ooi,
                            g.geo, (TS *)state, nsteps, ooi, energy, estride);
         return hipGetLastError();
     };
-    if (vol)
+    if (vol) {
+        if constexpr (std::is_same<TS, float>::value && std::is_same<TA, float>::value) {
+            // 128^2 Omega: four columns per lane in split bands, unless the
+            // two-column layout is asked for
+            if (g.ni == 128 && g.res_cols != 2 && g.res_rows != 16 && resident4_built(g.R2))
+                return resident4_launch_f32(g, state, nsteps, ooi, s, energy, estride);
+        }
         return g.ni == 64 ? go(k_resident<R2, 64, kResB, TS, TA, GAUSS, false, true>)
                           : go(k_resident<R2, 128, kResB, TS, TA, GAUSS, false, true>);
+    }
     if constexpr (std::is_same<TS, float>::value && std::is_same<TA, float>::value) {
         // four columns per lane where built, unless two are asked for (with
         // or without the energy trace, so that the trace runs the layout of

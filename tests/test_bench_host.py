@@ -59,17 +59,23 @@ def test_source_hash_tracks_the_kernel_sources(tmp_path, monkeypatch):
     h = bench.kernel_source_hash("k_resident4h")
     assert len(h) == 16 and int(h, 16) >= 0
     assert bench.kernel_source_hash("k_resident4h") == h
-    # a copy of the sources with one byte changed hashes differently
+    # copies of the sources: comments and blank lines added keep the hash,
+    # one changed token changes it
     csrc = os.path.join(ROOT, "paper_2310_10750_amd", "csrc")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     fake = tmp_path / "paper_2310_10750_amd" / "csrc"
     fake.mkdir(parents=True)
-    for f in bench.KERNEL_SOURCES["k_resident4h"]:
-        data = open(os.path.join(csrc, f), "rb").read()
-        if f == "kern_rowrun_impl.h":
-            data += b"\n"
-        (fake / f).write_bytes(data)
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.kernel_source_hash("k_resident4h") != h
+
+    def copy(extra):
+        for f in bench.KERNEL_SOURCES["k_resident4h"]:
+            data = open(os.path.join(csrc, f), "rb").read()
+            if f == "kern_rowrun_impl.h":
+                data += extra
+            (fake / f).write_bytes(data)
+        return bench.kernel_source_hash("k_resident4h")
+
+    assert copy(b"\n// a note\n/* and\n   another */\n\n") == h
+    assert copy(b"\nstatic_assert(true);\n") != h
 
 
 def test_stored_counters_are_consistent():

@@ -135,6 +135,51 @@ def test_volume_trajectory(orc, n, R2, kind, prec, algo):
         assert abs(o[i, 0] - own) <= 1e-12
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("R2", [1, 4, 9, 16, 25, 64])
+def test_volume_resident_layouts(orc, R2, kind):
+    """128^2 Omega inside its ring, FP32, LDS-resident: the default layout
+    (four columns per lane in split bands; the ring columns stay in the LDS
+    halo, the ring rows' fixed sums reach Omega's first and last m rows in
+    place of a neighbour's hand-over) against the oracle at every node after
+    one step, and against the two-column layout along 8 steps; the ring is
+    the projected input in both."""
+    print("volume resident layouts R2=%d kernel=%d" % (R2, kind), flush=True)
+    n = 128
+    out = {}
+    for shape in ((0, 0), (2, 16)):
+        nlch.nlch_set_resident_shape(*shape)
+        try:
+            for nsteps in (1, 8):
+                w, m = _workload(n, R2, kind, "f32", S=2, nsteps=nsteps)
+                b = DeviceBatch(w, "f32")
+                b.state.mul_(3.0)
+                b.init.copy_(b.state)
+                b.solve(nlch.NLCH_ALGO_RESIDENT)
+                torch.cuda.synchronize()
+                out[shape, nsteps] = (b, w, m)
+        finally:
+            nlch.nlch_set_resident_shape(0, 0)
+    b1, w, m = out[(0, 0), 1]
+    side = synth.state_side(m)
+    r = (side - n) // 2
+    ring = _ring_mask(side, r)
+    for i, s in enumerate(w.samples):
+        off = b1.samples[i].offset
+        U0 = b1.init[off:off + side * side].double().cpu().numpy().reshape(side, side)
+        got = b1.sample_state(i)
+        ref = vol.step(np.clip(U0, -1, 1), n, m.delta, m.kernel, s.amp, m.sigma, s.c_F,
+                       m.beta1, m.tau)
+        assert np.array_equal(got[ring], np.clip(U0, -1, 1)[ring])
+        assert np.max(np.abs(got[~ring] - ref[~ring])) <= ONE_STEP_TOL["f32"], i
+    b8, _, _ = out[(0, 0), 8]
+    c8, _, _ = out[(2, 16), 8]
+    for i in range(len(w.samples)):
+        assert np.max(np.abs(b8.sample_state(i) - c8.sample_state(i))) <= 1e-4, i
+        assert np.array_equal(b8.sample_state(i)[ring], c8.sample_state(i)[ring]), i
+    np.testing.assert_allclose(b8.ooi_host(), c8.ooi_host(), rtol=1e-6)
+
+
 @pytest.mark.parametrize("shape", [(2, 1, 0, 0, 0), (1, 2, 1, 0, 0), (2, 4, 2, 0, 0),
                                    (1, 8, 1, 0, 0), (1, 1, 0, 40, 0), (1, 1, 0, 0, 2),
                                    (2, 1, 0, 37, 2)])
