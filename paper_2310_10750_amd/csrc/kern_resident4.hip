@@ -337,8 +337,10 @@ __device__ __forceinline__ void row_windows_split(const float *win, Acc &&acc) {
 // kernel packs it contiguously (row stride n) over a halo that the next
 // publish rewrites anyway.
 // ---------------------------------------------------------------------------
+// The energy variant's FP64 sums do not fit the 128 registers of four waves
+// per SIMD without spilling; it runs at two (one sample per CU).
 template <int R2, bool GAUSS, bool ENERGY, bool VOL>
-__global__ __launch_bounds__(512, 4) void k_resident4h(
+__global__ __launch_bounds__(512, ENERGY ? 2 : 4) void k_resident4h(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, float *__restrict__ state, int nsteps,
     double *__restrict__ ooi, double *__restrict__ energy, int64_t estride) {
