@@ -819,10 +819,13 @@ __host__ __device__ constexpr size_t resident_lds_bytes(int n, int M, int B, siz
                 : (2 * (size_t)(n / B) + (vol ? 2 : 0)) * M * n * ta);
 }
 
+// In-place layouts: FP32 arithmetic keeps to the 128 registers that four
+// waves per SIMD allow; FP64, whose values take two registers each, would
+// spill there and may use 256 (two waves per SIMD).
 template <int R2, int N, int B, class TS, class TA, bool GAUSS, bool ENERGY, bool VOL,
           bool INPLACE = resident_inplace(N, Disc<R2>::M, B, sizeof(TS), sizeof(TA), ENERGY,
                                           VOL)>
-__global__ __launch_bounds__(512, INPLACE ? 4 : 1) void k_resident(
+__global__ __launch_bounds__(512, INPLACE ? (sizeof(TA) == 8 ? 2 : 4) : 1) void k_resident(
     const SampleDesc *__restrict__ sd, const int32_t *__restrict__ ids,
     const ModelGeo *__restrict__ geo, TS *__restrict__ state, int nsteps,
     double *__restrict__ ooi, double *__restrict__ energy, int64_t estride) {
