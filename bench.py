@@ -45,7 +45,7 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # Rates the peak-measurement program (paper_2310_10750_amd/peaks) reaches on
-# MI355X with this build's flags: FP32 adds, and LDS reads of 8 and 16 bytes
+# MI355X with the library's compile flags: FP32 adds, and LDS reads of 8 and 16 bytes
 # per lane (lane-contiguous).  No LDS bandwidth of CDNA4 is published beside
 # the 160 KB capacity; the measured rates are the LDS ceiling used here.
 MEASURED_ADD_TOPS = 71.9

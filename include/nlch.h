@@ -101,7 +101,7 @@ extern "C" {
 /* Status codes. */
 #define NLCH_OK 0
 #define NLCH_EINVAL (-1)       /* invalid argument (nothing enqueued)           */
-#define NLCH_EUNSUPPORTED (-2) /* valid model outside what this build supports  */
+#define NLCH_EUNSUPPORTED (-2) /* valid model outside what the library supports */
 #define NLCH_EDEVICE (-3)      /* HIP runtime error                              */
 #define NLCH_ENOMEM (-4)       /* internal table allocation failed               */
 
