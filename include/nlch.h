@@ -323,8 +323,10 @@ int nlch_set_stream_phases(int32_t phases);
 
 /* Layout of the LDS-resident (RESIDENT) kernel for later nlch_solve_batch
  * calls in this process, overriding the default and NLCH_ALGO_AUTOTUNE.
- * 128^2 lattices (FP32 state, periodic domain): each lane owns cols_per_lane
- * adjacent columns and walks rows_per_lane rows of a 16-row band.
+ * 128^2 lattices (FP32 state; periodic, or Omega inside its fixed ring, where
+ * (4, 8) and (2, 16) are built and (4, 16) runs as (2, 16)): each lane owns
+ * cols_per_lane adjacent columns and walks rows_per_lane rows of a 16-row
+ * band.
  *   (2, 16): one band per wave; every resident case.
  *   (4, 16): two bands per wave (one per half-wave), 16-byte LDS window
  *            loads; bit-identical to (2, 16).
